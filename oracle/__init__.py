@@ -1,0 +1,244 @@
+"""Python access to the plain FP64 CPU oracle (``oracle/lbm_oracle.c``).
+
+TEST INFRASTRUCTURE: only ``tests/``, the smoke check of ``__graft_entry__``
+and the CPU-baseline leg of ``bench.py`` use this package. It shares no code
+with the GPU path (``paper_2010_11751_amd``) and never imports it.
+
+Arrays are numpy FP64, populations in the layout named by the configuration
+(SoA ``pop[k][Ntot]`` or AoS ``pop[Ntot][Q]``), flags uint8 with FLUID=0,
+WALL=1, LID=2, linear cell index ``i = (x*ny + y)*nz + z`` (Sec. 2.5).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lbm_oracle.c")
+LIB = os.path.join(HERE, "liblbm_oracle.so")
+
+FLUID, WALL, LID = 0, 1, 2
+CAVITY, PERIODIC, CHANNEL = 0, 1, 2
+BGK, TRT, REG, RR = 0, 1, 2, 3
+SOA, AOS = 0, 1
+MODELS = {"bgk": BGK, "trt": TRT, "reg": REG, "rr": RR}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+             "-fopenmp", "-shared", SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("geometry", ctypes.c_int32), ("model", ctypes.c_int32),
+                ("layout", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("omega", ctypes.c_double), ("trt_lambda", ctypes.c_double),
+                ("omega_bulk", ctypes.c_double), ("u_lid", ctypes.c_double * 3),
+                ("force", ctypes.c_double * 3)]
+
+
+@dataclass
+class Config:
+    q: int = 19
+    nx: int = 8
+    ny: int = 8
+    nz: int = 8
+    geometry: int = CAVITY
+    model: int = BGK
+    layout: int = SOA
+    omega: float = 1.0
+    trt_lambda: float = 0.25
+    omega_bulk: float | None = None
+    u_lid: tuple = (0.0, 0.0, 0.0)
+    force: tuple = (0.0, 0.0, 0.0)
+
+    @property
+    def ntot(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def c_struct(self) -> _Cfg:
+        ob = self.omega if self.omega_bulk is None else self.omega_bulk
+        return _Cfg(self.q, self.nx, self.ny, self.nz, self.geometry, self.model, self.layout, 0,
+                    self.omega, self.trt_lambda, ob, (ctypes.c_double * 3)(*self.u_lid),
+                    (ctypes.c_double * 3)(*self.force))
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        cfgp = ctypes.POINTER(_Cfg)
+        L.oracle_lattice.argtypes = [ctypes.c_int, P, P, P]
+        L.oracle_neighbour_index.argtypes = [cfgp, ctypes.c_int64, ctypes.c_int]
+        L.oracle_neighbour_index.restype = ctypes.c_int64
+        L.oracle_flags.argtypes = [cfgp, P]
+        L.oracle_flags.restype = None
+        L.oracle_equilibrium.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, P, P]
+        L.oracle_equilibrium.restype = None
+        L.oracle_collide.argtypes = [cfgp, P, P]
+        L.oracle_init_state.argtypes = [cfgp, P, P, P, P]
+        L.oracle_reference_step.argtypes = [cfgp, P, P, P]
+        L.oracle_2pop_step.argtypes = [cfgp, P, P, P, P]
+        L.oracle_swap_step.argtypes = [cfgp, P, P, P]
+        L.oracle_aa_step.argtypes = [cfgp, P, P, ctypes.c_int, P]
+        L.oracle_aa_natural.argtypes = [cfgp, P, P, P]
+        L.oracle_macroscopic.argtypes = [cfgp, P, P, P, P]
+        L.oracle_invariants.argtypes = [cfgp, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc):
+    if rc != 0:
+        raise RuntimeError(f"oracle call failed with {rc}")
+
+
+def lattice(q: int):
+    """(c[q][3] int, t[q], opp[q]) in the oracle's velocity order."""
+    c = np.zeros((q, 3), np.int32)
+    t = np.zeros(q)
+    opp = np.zeros(q, np.int32)
+    _check(lib().oracle_lattice(q, _p(c), _p(t), _p(opp)))
+    return c, t, opp
+
+
+def flags(cfg: Config) -> np.ndarray:
+    fl = np.zeros(cfg.ntot, np.uint8)
+    lib().oracle_flags(ctypes.byref(cfg.c_struct()), _p(fl))
+    return fl
+
+
+def neighbour_index(cfg: Config, i: int, k: int) -> int:
+    return int(lib().oracle_neighbour_index(ctypes.byref(cfg.c_struct()), i, k))
+
+
+def equilibrium(q: int, rho: float, u, model: int = BGK) -> np.ndarray:
+    E = np.zeros(q)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    lib().oracle_equilibrium(q, model, float(rho), _p(uu), _p(E))
+    return E
+
+
+def collide(cfg: Config, f) -> np.ndarray:
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros(cfg.q)
+    _check(lib().oracle_collide(ctypes.byref(cfg.c_struct()), _p(f), _p(out)))
+    return out
+
+
+def init_state(cfg: Config, fl: np.ndarray, rho=None, u=None) -> np.ndarray:
+    """Wall terms in wall cells, E(rho, u) in fluid cells; u is u[3][Ntot]."""
+    pop = np.zeros(cfg.ntot * cfg.q)
+    r = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64).ravel()
+    v = None if u is None else np.ascontiguousarray(u, dtype=np.float64).ravel()
+    _check(lib().oracle_init_state(ctypes.byref(cfg.c_struct()), _p(fl), _p(r), _p(v), _p(pop)))
+    return pop
+
+
+def reference_step(cfg: Config, fl, f) -> np.ndarray:
+    new = np.empty_like(f)
+    _check(lib().oracle_reference_step(ctypes.byref(cfg.c_struct()), _p(fl), _p(f), _p(new)))
+    return new
+
+
+def twopop_step(cfg: Config, fl, pop, out, order=None) -> None:
+    _check(lib().oracle_2pop_step(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), _p(out), _p(order)))
+
+
+def swap_step(cfg: Config, fl, pop, order=None) -> None:
+    _check(lib().oracle_swap_step(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), _p(order)))
+
+
+def aa_step(cfg: Config, fl, pop, odd: bool, order=None) -> None:
+    _check(lib().oracle_aa_step(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), int(bool(odd)), _p(order)))
+
+
+def aa_natural(cfg: Config, fl, pop) -> np.ndarray:
+    f = np.empty_like(pop)
+    _check(lib().oracle_aa_natural(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), _p(f)))
+    return f
+
+
+def macroscopic(cfg: Config, fl, f):
+    rho = np.zeros(cfg.ntot)
+    u = np.zeros(3 * cfg.ntot)
+    _check(lib().oracle_macroscopic(ctypes.byref(cfg.c_struct()), _p(fl), _p(f), _p(rho), _p(u)))
+    return rho, u.reshape(3, cfg.ntot)
+
+
+def invariants(cfg: Config, fl, f):
+    m = ctypes.c_double()
+    e = ctypes.c_double()
+    _check(lib().oracle_invariants(ctypes.byref(cfg.c_struct()), _p(fl), _p(f),
+                                   ctypes.byref(m), ctypes.byref(e)))
+    return m.value, e.value
+
+
+def to_soa(cfg: Config, pop) -> np.ndarray:
+    """Populations of any layout as the natural f[k][Ntot] array."""
+    if cfg.layout == SOA:
+        return pop.reshape(cfg.q, cfg.ntot).copy()
+    return pop.reshape(cfg.ntot, cfg.q).T.copy()
+
+
+class Simulation:
+    """Runs the oracle with one of the three schemes of Table 1 and reads back
+    the natural pre-collision populations f[k][Ntot] at whole steps."""
+
+    def __init__(self, cfg: Config, scheme: str = "2pop", rho=None, u=None, order=None):
+        self.cfg, self.scheme, self.order = cfg, scheme, order
+        self.flags = flags(cfg)
+        self.pop = init_state(cfg, self.flags, rho, u)
+        self.out = self.pop.copy() if scheme == "2pop" else None
+        self.t = 0
+
+    def step(self, n: int = 1) -> None:
+        for _ in range(n):
+            if self.scheme == "ref":
+                self.pop = reference_step(self.cfg, self.flags, self.pop)
+            elif self.scheme == "2pop":
+                twopop_step(self.cfg, self.flags, self.pop, self.out, self.order)
+                self.pop, self.out = self.out, self.pop
+            elif self.scheme == "swap":
+                swap_step(self.cfg, self.flags, self.pop, self.order)
+            elif self.scheme == "aa":
+                aa_step(self.cfg, self.flags, self.pop, self.t % 2 == 1, self.order)
+            else:
+                raise ValueError(self.scheme)
+            self.t += 1
+
+    def natural(self) -> np.ndarray:
+        """Pre-collision populations in the configured layout."""
+        if self.scheme == "aa" and self.t % 2 == 1:
+            return aa_natural(self.cfg, self.flags, self.pop)
+        return self.pop.copy()
+
+    def populations(self) -> np.ndarray:
+        """f[k][Ntot] (natural SoA)."""
+        return to_soa(self.cfg, self.natural())
+
+    def macroscopic(self):
+        return macroscopic(self.cfg, self.flags, self.natural())
+
+    def invariants(self):
+        return invariants(self.cfg, self.flags, self.natural())

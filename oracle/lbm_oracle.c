@@ -1,0 +1,649 @@
+/*
+ * Plain FP64 CPU oracle of the lattice Boltzmann collide-and-stream step of
+ * Latt, Coreixas & Beny, "Cross-platform programming model for many-core
+ * lattice Boltzmann simulation" (arXiv:2010.11751).
+ *
+ * TEST INFRASTRUCTURE. Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load this file's library. The GPU product path shares
+ * no code, header, table or helper with it.
+ *
+ * Written for obviousness, not speed: one cell at a time, loops over the
+ * discrete velocities, the paper's notation (f, f_out, pop, out, tmp, c_k,
+ * t_k, k-bar), FP64 throughout. Build with -ffp-contract=off.
+ *
+ * Parity status of each part (what pins it lives in tests/test_oracle_*.py):
+ *   lattice tables ............ pinned (isotropy identities, worked f_out_0 /
+ *                               f_out_10 relation of Sec. 2.6)
+ *   equilibrium, BGK, TRT ..... pinned (closed-form moments, Eq. symmetry_Ek,
+ *                               conservation, fixed point, TRT->BGK limit,
+ *                               Taylor-Green decay, Couette, Poiseuille)
+ *   REG ....................... pinned (stress relation, w=1 -> equilibrium,
+ *                               bulk knob reduces to single relaxation)
+ *   RR ........................ equilibrium pinned (D3Q27 product form),
+ *                               third/fourth-order recursion: parity unpinned
+ *                               (the paper's RR formulas are in an absent
+ *                               reference; pinned only by the invariants and
+ *                               reductions above)
+ *   reference step, schemes ... pinned (np.roll brute force, bounce-back
+ *                               permutation, mass conservation, schemes and
+ *                               layouts agree bit for bit, shuffled order)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Configuration, as passed from Python (ctypes Structure of the same shape). */
+
+enum { O_FLUID = 0, O_WALL = 1, O_LID = 2 };
+enum { O_CAVITY = 0, O_PERIODIC = 1, O_CHANNEL = 2 };
+enum { O_BGK = 0, O_TRT = 1, O_REG = 2, O_RR = 3 };
+enum { O_SOA = 0, O_AOS = 1 };
+
+typedef struct {
+    int32_t q, nx, ny, nz;
+    int32_t geometry; /* O_CAVITY, O_PERIODIC, O_CHANNEL                       */
+    int32_t model;    /* O_BGK, O_TRT, O_REG, O_RR                             */
+    int32_t layout;   /* O_SOA: pop[k][Ntot], O_AOS: pop[Ntot][Q]              */
+    int32_t pad_;
+    double omega;      /* shear relaxation frequency omega_nu                  */
+    double trt_lambda; /* TRT "magic" parameter                                */
+    double omega_bulk; /* bulk relaxation frequency omega_nu_b (REG, RR)       */
+    double u_lid[3];   /* velocity u_w of LID cells                            */
+    double force[3];   /* test-only uniform body force; zero for the method    */
+} ocfg;
+
+/* ------------------------------------------------------------------------- */
+/* Lattices (Sec. 2.1 refers to the textbook stencils; weights are the
+ * standard D3Q19 / D3Q27 ones). Velocity order: first the velocities whose
+ * first nonzero component is -1 (by number of nonzeros, then
+ * lexicographically), then the rest velocity, then the negatives of the first
+ * half in the same order; this is the order that puts c_0=(-1,0,0)=-c_10 as
+ * the worked example of Sec. 2.6 requires. */
+
+typedef struct {
+    int q, rest;
+    int c[27][3];
+    double t[27];
+    int opp[27];
+} olat;
+
+static const int Q19_HALF[9][3] = {
+    {-1, 0, 0}, {0, -1, 0}, {0, 0, -1},
+    {-1, -1, 0}, {-1, 0, -1}, {-1, 0, 1}, {-1, 1, 0}, {0, -1, -1}, {0, -1, 1}};
+static const int Q27_HALF[13][3] = {
+    {-1, 0, 0}, {0, -1, 0}, {0, 0, -1},
+    {-1, -1, 0}, {-1, 0, -1}, {-1, 0, 1}, {-1, 1, 0}, {0, -1, -1}, {0, -1, 1},
+    {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}};
+
+static int make_lattice(int q, olat *L)
+{
+    int half, k, a;
+    const int (*h)[3];
+    if (q == 19) { half = 9; h = Q19_HALF; }
+    else if (q == 27) { half = 13; h = Q27_HALF; }
+    else return -1;
+    L->q = q;
+    L->rest = half;
+    for (a = 0; a < 3; ++a) L->c[half][a] = 0;
+    for (k = 0; k < half; ++k)
+        for (a = 0; a < 3; ++a) {
+            L->c[k][a] = h[k][a];
+            L->c[k + half + 1][a] = -h[k][a];
+        }
+    for (k = 0; k < q; ++k) {
+        int nnz = abs(L->c[k][0]) + abs(L->c[k][1]) + abs(L->c[k][2]);
+        if (q == 19) L->t[k] = nnz == 0 ? 1.0 / 3.0 : nnz == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
+        else L->t[k] = nnz == 0 ? 8.0 / 27.0 : nnz == 1 ? 2.0 / 27.0 : nnz == 2 ? 1.0 / 54.0 : 1.0 / 216.0;
+        L->opp[k] = k == half ? half : (k < half ? k + half + 1 : k - half - 1);
+    }
+    return 0;
+}
+
+int oracle_lattice(int q, int32_t *c, double *t, int32_t *opp)
+{
+    olat L;
+    int k, a;
+    if (make_lattice(q, &L)) return -1;
+    for (k = 0; k < q; ++k) {
+        for (a = 0; a < 3; ++a) c[3 * k + a] = L.c[k][a];
+        t[k] = L.t[k];
+        opp[k] = L.opp[k];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Indexing (Sec. 2.5): linear index i = (x*ny + y)*nz + z, z fastest.
+ * Neighbour coordinates wrap modulo the box, which only matters for periodic
+ * axes: in a cavity a fluid cell's neighbours are always inside the box. */
+
+static int64_t cell_index(const ocfg *g, int64_t x, int64_t y, int64_t z)
+{
+    return (x * g->ny + y) * g->nz + z;
+}
+
+static void cell_xyz(const ocfg *g, int64_t i, int64_t *x, int64_t *y, int64_t *z)
+{
+    *x = i / ((int64_t)g->ny * g->nz);
+    *y = (i % ((int64_t)g->ny * g->nz)) / g->nz;
+    *z = i % g->nz;
+}
+
+static int64_t wrap(int64_t v, int64_t n) { return ((v % n) + n) % n; }
+
+/* Index of the cell at x + s*c (s = +1 or -1). */
+static int64_t neighbour(const ocfg *g, int64_t i, const int *c, int s)
+{
+    int64_t x, y, z;
+    cell_xyz(g, i, &x, &y, &z);
+    return cell_index(g, wrap(x + s * c[0], g->nx), wrap(y + s * c[1], g->ny),
+                      wrap(z + s * c[2], g->nz));
+}
+
+static int64_t ntot(const ocfg *g) { return (int64_t)g->nx * g->ny * g->nz; }
+
+/* Address of population k of cell i in the configured layout (Sec. 2.3). */
+static int64_t at(const ocfg *g, int64_t i, int k)
+{
+    return g->layout == O_AOS ? i * g->q + k : (int64_t)k * ntot(g) + i;
+}
+
+int64_t oracle_neighbour_index(const ocfg *g, int64_t i, int k)
+{
+    olat L;
+    if (make_lattice(g->q, &L)) return -1;
+    return neighbour(g, i, L.c[k], +1);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Geometry. Cavity: fluid inside, one wall layer on every face, the whole
+ * top layer z = nz-1 (edges and corners included) is the moving lid.
+ * Periodic: every cell is fluid. Channel: periodic in x and y, a wall at
+ * z = 0 and the lid at z = nz-1. */
+
+void oracle_flags(const ocfg *g, uint8_t *flags)
+{
+    int64_t x, y, z;
+    for (x = 0; x < g->nx; ++x)
+        for (y = 0; y < g->ny; ++y)
+            for (z = 0; z < g->nz; ++z) {
+                uint8_t f = O_FLUID;
+                if (g->geometry == O_CAVITY) {
+                    int inside = x >= 1 && x <= g->nx - 2 && y >= 1 && y <= g->ny - 2 &&
+                                 z >= 1 && z <= g->nz - 2;
+                    if (!inside) f = (z == g->nz - 1) ? O_LID : O_WALL;
+                } else if (g->geometry == O_CHANNEL) {
+                    if (z == 0) f = O_WALL;
+                    else if (z == g->nz - 1) f = O_LID;
+                }
+                flags[cell_index(g, x, y, z)] = f;
+            }
+}
+
+/* Momentum-exchange term of Eq. momentum-exchange with rho_w = 1:
+ * w_k = -6 t_k c_k . u_w, stored by wall cells (Eq. storage2). */
+static double wall_term(const olat *L, const ocfg *g, uint8_t flag, int k)
+{
+    double uw[3] = {0.0, 0.0, 0.0};
+    if (flag == O_LID) { uw[0] = g->u_lid[0]; uw[1] = g->u_lid[1]; uw[2] = g->u_lid[2]; }
+    return -6.0 * L->t[k] * (L->c[k][0] * uw[0] + L->c[k][1] * uw[1] + L->c[k][2] * uw[2]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Moments and equilibria. */
+
+static void density_velocity(const olat *L, const double *f, double *rho, double u[3])
+{
+    int k, a;
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (k = 0; k < L->q; ++k) {
+        r += f[k];
+        for (a = 0; a < 3; ++a) j[a] += L->c[k][a] * f[k];
+    }
+    *rho = r;
+    for (a = 0; a < 3; ++a) u[a] = j[a] / r;
+}
+
+/* BGK-W2 second-order weighted equilibrium (Sec. 2.6), with the |u|^2
+ * coefficient 3/2 = 1/(2 c_s^2) that makes sum_k E_k = rho. */
+static void equilibrium2(const olat *L, double rho, const double u[3], double *E)
+{
+    int k;
+    double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (k = 0; k < L->q; ++k) {
+        double cu = L->c[k][0] * u[0] + L->c[k][1] * u[1] + L->c[k][2] * u[2];
+        E[k] = rho * L->t[k] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+    }
+}
+
+/* Hermite machinery for the recursive-regularized model. A multi-index
+ * n = (nx, ny, nz) with entries in {0,1,2}; per axis h_0 = 1, h_1(c) = c,
+ * h_2(c) = c^2 - 1/3 (c_s^2 = 1/3); H_n(c) is the product over the axes and
+ * its norm is N_n = nx! ny! nz! (1/3)^(nx+ny+nz). */
+static double hermite_1d(int n, int c)
+{
+    return n == 0 ? 1.0 : n == 1 ? (double)c : (double)(c * c) - 1.0 / 3.0;
+}
+
+static double hermite(const int n[3], const int c[3])
+{
+    return hermite_1d(n[0], c[0]) * hermite_1d(n[1], c[1]) * hermite_1d(n[2], c[2]);
+}
+
+static double hermite_norm(const int n[3])
+{
+    double v = 1.0;
+    int a, m;
+    for (a = 0; a < 3; ++a)
+        for (m = 0; m < n[a]; ++m) v *= (m + 1) / 3.0;
+    return v;
+}
+
+/* Supported Hermite set S: all of {0,1,2}^3 on D3Q27; on D3Q19 every n of
+ * order <= 2 plus the six permutations of (2,1,0). */
+static int in_support(int q, const int n[3])
+{
+    int order = n[0] + n[1] + n[2];
+    int twos = (n[0] == 2) + (n[1] == 2) + (n[2] == 2);
+    int ones = (n[0] == 1) + (n[1] == 1) + (n[2] == 1);
+    if (q == 27) return 1;
+    if (order <= 2) return 1;
+    return order == 3 && twos == 1 && ones == 1;
+}
+
+/* Equilibrium of the recursive-regularized model: the Hermite expansion of
+ * the Maxwellian restricted to S, E_k = t_k rho sum_n H_n(c_k) u^n / N_n. */
+static void equilibrium_rr(const olat *L, double rho, const double u[3], double *E)
+{
+    int k, n[3];
+    for (k = 0; k < L->q; ++k) {
+        double s = 0.0;
+        for (n[0] = 0; n[0] <= 2; ++n[0])
+            for (n[1] = 0; n[1] <= 2; ++n[1])
+                for (n[2] = 0; n[2] <= 2; ++n[2]) {
+                    if (!in_support(L->q, n)) continue;
+                    s += hermite(n, L->c[k]) * pow(u[0], n[0]) * pow(u[1], n[1]) *
+                         pow(u[2], n[2]) / hermite_norm(n);
+                }
+        E[k] = L->t[k] * rho * s;
+    }
+}
+
+void oracle_equilibrium(int q, int model, double rho, const double *u, double *E)
+{
+    olat L;
+    if (make_lattice(q, &L)) return;
+    if (model == O_RR) equilibrium_rr(&L, rho, u, E);
+    else equilibrium2(&L, rho, u, E);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Collision models (Sec. 2.2, Sec. 2.6). */
+
+/* TRT antisymmetric rate from the magic parameter
+ * Lambda = (1/omega_plus - 1/2)(1/omega_minus - 1/2). */
+static double trt_omega_minus(double omega_plus, double lambda)
+{
+    return 1.0 / (0.5 + lambda / (1.0 / omega_plus - 0.5));
+}
+
+/* Relaxed second-order non-equilibrium stress. The bulk-viscosity knob of
+ * Eq. bulk, read with (M - M^eq) in place of the printed (M^eq - M^eq): the
+ * deviatoric part relaxes with omega_nu, the trace with omega_nu_b. */
+static void relaxed_stress(double omega, double omega_bulk, double P[3][3])
+{
+    int a, b;
+    double tr3 = (P[0][0] + P[1][1] + P[2][2]) / 3.0;
+    for (a = 0; a < 3; ++a)
+        for (b = 0; b < 3; ++b) {
+            double dev = P[a][b] - (a == b ? tr3 : 0.0);
+            P[a][b] = (1.0 - omega) * dev + (a == b ? (1.0 - omega_bulk) * tr3 : 0.0);
+        }
+}
+
+static void noneq_stress(const olat *L, const double *f, const double *E, double P[3][3])
+{
+    int k, a, b;
+    for (a = 0; a < 3; ++a)
+        for (b = 0; b < 3; ++b) P[a][b] = 0.0;
+    for (k = 0; k < L->q; ++k)
+        for (a = 0; a < 3; ++a)
+            for (b = 0; b < 3; ++b) P[a][b] += L->c[k][a] * L->c[k][b] * (f[k] - E[k]);
+}
+
+/* Non-equilibrium Hermite coefficient a1_n for |n| >= 2 by the pair-sum
+ * recursion: a1_{a1..am} = sum over pairs l<j of (prod of u over the other
+ * indices) * Pi*_{al aj}; at order 2 this is just Pi*_{ab}. */
+static double a1_coefficient(const int n[3], const double u[3], double P[3][3])
+{
+    int idx[6], m = 0, a, r, l, j;
+    double s = 0.0;
+    for (a = 0; a < 3; ++a)
+        for (r = 0; r < n[a]; ++r) idx[m++] = a;
+    for (l = 0; l < m; ++l)
+        for (j = l + 1; j < m; ++j) {
+            double prod = P[idx[l]][idx[j]];
+            for (r = 0; r < m; ++r)
+                if (r != l && r != j) prod *= u[idx[r]];
+            s += prod;
+        }
+    return s;
+}
+
+static void collide(const olat *L, const ocfg *g, const double *f, double *fout)
+{
+    int k, a, b;
+    double rho, u[3], E[27];
+    density_velocity(L, f, &rho, u);
+
+    if (g->model == O_BGK) {
+        equilibrium2(L, rho, u, E);
+        for (k = 0; k < L->q; ++k) fout[k] = f[k] - g->omega * (f[k] - E[k]);
+    } else if (g->model == O_TRT) {
+        double wp = g->omega, wm = trt_omega_minus(g->omega, g->trt_lambda);
+        equilibrium2(L, rho, u, E);
+        for (k = 0; k < L->q; ++k) {
+            int kb = L->opp[k];
+            double fp = 0.5 * (f[k] + f[kb]), fm = 0.5 * (f[k] - f[kb]);
+            double ep = 0.5 * (E[k] + E[kb]), em = 0.5 * (E[k] - E[kb]);
+            fout[k] = f[k] - wp * (fp - ep) - wm * (fm - em);
+        }
+    } else if (g->model == O_REG) {
+        double P[3][3];
+        equilibrium2(L, rho, u, E);
+        noneq_stress(L, f, E, P);
+        relaxed_stress(g->omega, g->omega_bulk, P);
+        for (k = 0; k < L->q; ++k) {
+            double s = 0.0;
+            for (a = 0; a < 3; ++a)
+                for (b = 0; b < 3; ++b)
+                    s += (L->c[k][a] * L->c[k][b] - (a == b ? 1.0 / 3.0 : 0.0)) * P[a][b];
+            fout[k] = E[k] + L->t[k] * 4.5 * s;
+        }
+    } else { /* O_RR */
+        double P[3][3];
+        int n[3];
+        equilibrium_rr(L, rho, u, E);
+        noneq_stress(L, f, E, P);
+        relaxed_stress(g->omega, g->omega_bulk, P);
+        for (k = 0; k < L->q; ++k) {
+            double s = 0.0;
+            for (n[0] = 0; n[0] <= 2; ++n[0])
+                for (n[1] = 0; n[1] <= 2; ++n[1])
+                    for (n[2] = 0; n[2] <= 2; ++n[2]) {
+                        if (n[0] + n[1] + n[2] < 2 || !in_support(L->q, n)) continue;
+                        s += hermite(n, L->c[k]) * a1_coefficient(n, u, P) / hermite_norm(n);
+                    }
+            fout[k] = E[k] + L->t[k] * s;
+        }
+    }
+
+    /* Test-only body force (not part of the paper's method): first-order
+     * source 3 t_k c_k . F added to the outgoing populations. */
+    if (g->force[0] != 0.0 || g->force[1] != 0.0 || g->force[2] != 0.0)
+        for (k = 0; k < L->q; ++k)
+            fout[k] += 3.0 * L->t[k] *
+                       (L->c[k][0] * g->force[0] + L->c[k][1] * g->force[1] +
+                        L->c[k][2] * g->force[2]);
+}
+
+int oracle_collide(const ocfg *g, const double *f, double *fout)
+{
+    olat L;
+    if (make_lattice(g->q, &L)) return -1;
+    collide(&L, g, f, fout);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* State set-up: wall cells hold their momentum-exchange terms in every slot
+ * (Eq. storage2), fluid cells hold E(rho, u) (Eq. storage1). rho and u may be
+ * NULL (rho = 1, u = 0); u is given as u[3][Ntot]. The equilibrium is the
+ * model's own (E^S for RR). */
+int oracle_init_state(const ocfg *g, const uint8_t *flags, const double *rho,
+                      const double *u, double *pop)
+{
+    olat L;
+    int64_t i, n = ntot(g);
+    int k;
+    if (make_lattice(g->q, &L)) return -1;
+    for (i = 0; i < n; ++i) {
+        if (flags[i] != O_FLUID) {
+            for (k = 0; k < L.q; ++k) pop[at(g, i, k)] = wall_term(&L, g, flags[i], k);
+        } else {
+            double r = rho ? rho[i] : 1.0, v[3] = {0.0, 0.0, 0.0}, E[27];
+            if (u) { v[0] = u[i]; v[1] = u[n + i]; v[2] = u[2 * n + i]; }
+            if (g->model == O_RR) equilibrium_rr(&L, r, v, E);
+            else equilibrium2(&L, r, v, E);
+            for (k = 0; k < L.q; ++k) pop[at(g, i, k)] = E[k];
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Reference step, free of any memory-access scheme (Sec. 2.1):
+ * collide every fluid cell, then every fluid cell x gathers population k from
+ * its upstream neighbour s = x - c_k; if s is not fluid the link is bounced
+ * back at the half-way wall, f_k(x) = f_out_kbar(x) + w_kbar(s)
+ * (Eq. momentum-exchange with k and k-bar exchanged). The rest population
+ * stays. Wall cells keep their stored terms. fnew must not alias f. */
+int oracle_reference_step(const ocfg *g, const uint8_t *flags, const double *f, double *fnew)
+{
+    olat L;
+    int64_t i, n = ntot(g);
+    double *fo;
+    if (make_lattice(g->q, &L)) return -1;
+    fo = (double *)malloc(sizeof(double) * (size_t)n * L.q);
+    if (!fo) return -2;
+
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; ++i) {
+        double cell[27], out[27];
+        int k;
+        if (flags[i] != O_FLUID) continue;
+        for (k = 0; k < L.q; ++k) cell[k] = f[at(g, i, k)];
+        collide(&L, g, cell, out);
+        for (k = 0; k < L.q; ++k) fo[at(g, i, k)] = out[k];
+    }
+
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; ++i) {
+        int k;
+        if (flags[i] != O_FLUID) {
+            for (k = 0; k < L.q; ++k) fnew[at(g, i, k)] = f[at(g, i, k)];
+            continue;
+        }
+        for (k = 0; k < L.q; ++k) {
+            int64_t s;
+            if (k == L.rest) { fnew[at(g, i, k)] = fo[at(g, i, k)]; continue; }
+            s = neighbour(g, i, L.c[k], -1);
+            if (flags[s] == O_FLUID) fnew[at(g, i, k)] = fo[at(g, s, k)];
+            else fnew[at(g, i, k)] = fo[at(g, i, L.opp[k])] + wall_term(&L, g, flags[s], L.opp[k]);
+        }
+    }
+    free(fo);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The three memory-access schemes of Table 1, executed on fluid cells in the
+ * order given by `order` (a permutation of 0..Ntot-1; NULL = natural order).
+ * Order independence is what makes them thread safe (Sec. 2.3). */
+
+static int64_t pick(const int64_t *order, int64_t j) { return order ? order[j] : j; }
+
+/* Double-population scheme: collide pop, stream into out; the caller then
+ * exchanges the two arrays. Both arrays hold the wall terms in wall cells. */
+int oracle_2pop_step(const ocfg *g, const uint8_t *flags, const double *pop, double *out,
+                     const int64_t *order)
+{
+    olat L;
+    int64_t j, n = ntot(g);
+    if (make_lattice(g->q, &L)) return -1;
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < n; ++j) {
+        int64_t i = pick(order, j);
+        double cell[27], fo[27];
+        int k;
+        if (flags[i] != O_FLUID) continue;
+        for (k = 0; k < L.q; ++k) cell[k] = pop[at(g, i, k)];
+        collide(&L, g, cell, fo);
+        for (k = 0; k < L.q; ++k) {
+            int64_t nb;
+            if (k == L.rest) { out[at(g, i, k)] = fo[k]; continue; }
+            nb = neighbour(g, i, L.c[k], +1);
+            if (flags[nb] == O_FLUID) out[at(g, nb, k)] = fo[k];              /* nb_out_k <- pop_k        */
+            else out[at(g, i, L.opp[k])] = fo[k] + pop[at(g, nb, k)];        /* out_kbar <- pop_k + nb_pop_k */
+        }
+    }
+    return 0;
+}
+
+/* Swap algorithm, split into a collision sweep and a streaming sweep over the
+ * nine (thirteen on D3Q27) directions k < rest. The wall cells' duty of the
+ * Table 1 caption is read as an accumulation nb_pop_k += pop_kbar, which is
+ * the only reading that keeps the fluid population it would otherwise
+ * discard. */
+int oracle_swap_step(const ocfg *g, const uint8_t *flags, double *pop, const int64_t *order)
+{
+    olat L;
+    int64_t j, n = ntot(g);
+    if (make_lattice(g->q, &L)) return -1;
+
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < n; ++j) {
+        int64_t i = pick(order, j);
+        double cell[27], fo[27];
+        int k;
+        if (flags[i] != O_FLUID) continue;
+        for (k = 0; k < L.q; ++k) cell[k] = pop[at(g, i, k)];
+        collide(&L, g, cell, fo);
+        for (k = 0; k < L.q; ++k) pop[at(g, i, L.opp[k])] = fo[k];           /* pop_kbar <- Omega_k(pop) */
+    }
+
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < n; ++j) {
+        int64_t i = pick(order, j);
+        int k;
+        for (k = 0; k < L.rest; ++k) {
+            int64_t nb = neighbour(g, i, L.c[k], +1);
+            if (flags[i] == O_FLUID) {
+                if (flags[nb] == O_FLUID) {                                  /* pop_kbar <-> nb_pop_k */
+                    double tmp = pop[at(g, i, L.opp[k])];
+                    pop[at(g, i, L.opp[k])] = pop[at(g, nb, k)];
+                    pop[at(g, nb, k)] = tmp;
+                } else {                                                     /* pop_kbar += nb_pop_k */
+                    pop[at(g, i, L.opp[k])] = pop[at(g, i, L.opp[k])] + pop[at(g, nb, k)];
+                }
+            } else if (flags[nb] == O_FLUID) {                               /* wall: nb_pop_k += pop_kbar */
+                pop[at(g, nb, k)] = pop[at(g, nb, k)] + pop[at(g, i, L.opp[k])];
+            }
+        }
+    }
+    return 0;
+}
+
+/* AA-pattern. Even step: purely local, post-collision values at opposite
+ * slots. Odd step: pull f_k(x) from pop_kbar(x - c_k) (the streaming equation
+ * fixes the upstream cell), or pop_k(x) + pop_kbar(x - c_k) across a wall;
+ * collide; push f_out_k to pop_k(x + c_k), or pop_kbar(x) <- f_out_k +
+ * pop_k(x + c_k) across a wall. The rest population stays local. */
+int oracle_aa_step(const ocfg *g, const uint8_t *flags, double *pop, int odd, const int64_t *order)
+{
+    olat L;
+    int64_t j, n = ntot(g);
+    if (make_lattice(g->q, &L)) return -1;
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < n; ++j) {
+        int64_t i = pick(order, j);
+        double tmp[27], fo[27];
+        int k;
+        if (flags[i] != O_FLUID) continue;
+        if (!odd) {
+            for (k = 0; k < L.q; ++k) tmp[k] = pop[at(g, i, k)];
+            collide(&L, g, tmp, fo);
+            for (k = 0; k < L.q; ++k) pop[at(g, i, L.opp[k])] = fo[k];
+            continue;
+        }
+        for (k = 0; k < L.q; ++k) {
+            int64_t s;
+            if (k == L.rest) { tmp[k] = pop[at(g, i, k)]; continue; }
+            s = neighbour(g, i, L.c[k], -1);
+            if (flags[s] == O_FLUID) tmp[k] = pop[at(g, s, L.opp[k])];
+            else tmp[k] = pop[at(g, i, k)] + pop[at(g, s, L.opp[k])];
+        }
+        collide(&L, g, tmp, fo);
+        for (k = 0; k < L.q; ++k) {
+            int64_t nb;
+            if (k == L.rest) { pop[at(g, i, k)] = fo[k]; continue; }
+            nb = neighbour(g, i, L.c[k], +1);
+            if (flags[nb] == O_FLUID) pop[at(g, nb, k)] = fo[k];
+            else pop[at(g, i, L.opp[k])] = fo[k] + pop[at(g, nb, k)];
+        }
+    }
+    return 0;
+}
+
+/* Natural pre-collision populations of an AA array left by an even step:
+ * the odd-step pull without the collision. Wall cells copy their terms. */
+int oracle_aa_natural(const ocfg *g, const uint8_t *flags, const double *pop, double *f)
+{
+    olat L;
+    int64_t i, n = ntot(g);
+    if (make_lattice(g->q, &L)) return -1;
+    for (i = 0; i < n; ++i) {
+        int k;
+        for (k = 0; k < L.q; ++k) {
+            int64_t s;
+            if (flags[i] != O_FLUID || k == L.rest) { f[at(g, i, k)] = pop[at(g, i, k)]; continue; }
+            s = neighbour(g, i, L.c[k], -1);
+            if (flags[s] == O_FLUID) f[at(g, i, k)] = pop[at(g, s, L.opp[k])];
+            else f[at(g, i, k)] = pop[at(g, i, k)] + pop[at(g, s, L.opp[k])];
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Read-outs. Density and velocity of every fluid cell (0 on wall cells);
+ * u is written as u[3][Ntot]. */
+int oracle_macroscopic(const ocfg *g, const uint8_t *flags, const double *f, double *rho, double *u)
+{
+    olat L;
+    int64_t i, n = ntot(g);
+    if (make_lattice(g->q, &L)) return -1;
+    for (i = 0; i < n; ++i) {
+        double cell[27], r, v[3];
+        int k;
+        if (flags[i] != O_FLUID) { rho[i] = 0.0; u[i] = u[n + i] = u[2 * n + i] = 0.0; continue; }
+        for (k = 0; k < L.q; ++k) cell[k] = f[at(g, i, k)];
+        density_velocity(&L, cell, &r, v);
+        rho[i] = r;
+        u[i] = v[0]; u[n + i] = v[1]; u[2 * n + i] = v[2];
+    }
+    return 0;
+}
+
+/* Global mass sum_fluid sum_k f_k and kinetic energy 1/2 sum_fluid rho |u|^2,
+ * accumulated in long double in index order. */
+int oracle_invariants(const ocfg *g, const uint8_t *flags, const double *f, double *mass, double *ke)
+{
+    olat L;
+    int64_t i, n = ntot(g);
+    long double m = 0.0L, e = 0.0L;
+    if (make_lattice(g->q, &L)) return -1;
+    for (i = 0; i < n; ++i) {
+        double cell[27], r, v[3];
+        int k;
+        if (flags[i] != O_FLUID) continue;
+        for (k = 0; k < L.q; ++k) { cell[k] = f[at(g, i, k)]; m += cell[k]; }
+        density_velocity(&L, cell, &r, v);
+        e += 0.5L * r * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    }
+    *mass = (double)m;
+    *ke = (double)e;
+    return 0;
+}

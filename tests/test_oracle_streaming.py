@@ -1,0 +1,173 @@
+"""Pins of the oracle's streaming, bounce-back and memory-access schemes:
+np.roll brute force on a periodic box, push-form brute force of the
+bounce-back / momentum-exchange rule (Eq. momentum-exchange), mass and
+momentum conservation, and bit-exact agreement of the three schemes of
+Table 1, both layouts and any traversal order (Sec. 2.3)."""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2010_11751_amd import workloads as W
+
+SCHEMES = ("ref", "2pop", "swap", "aa")
+
+
+def soa(cfg, f_cells):
+    """Random cell-major populations -> layout of cfg."""
+    if cfg.layout == 0:
+        return np.ascontiguousarray(f_cells.T).ravel()
+    return np.ascontiguousarray(f_cells).ravel()
+
+
+@pytest.mark.parametrize("q", (19, 27))
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_periodic_streaming_is_np_roll(orc, q, scheme):
+    """omega = 0 makes collision the identity; one step must then move every
+    population k by c_k on the periodic box."""
+    nx, ny, nz = 4, 5, 6
+    cfg = orc.Config(q=q, nx=nx, ny=ny, nz=nz, geometry=orc.PERIODIC, omega=0.0)
+    c, _, _ = orc.lattice(q)
+    f0 = W.random_populations(41, q, cfg.ntot)
+    sim = orc.Simulation(cfg, scheme)
+    sim.pop[:] = soa(cfg, f0)
+    if sim.out is not None:
+        sim.out[:] = sim.pop
+    for steps in (1, 2, 3):
+        sim.step(1)
+        got = sim.populations()
+        for k in range(q):
+            want = np.roll(f0[:, k].reshape(nx, ny, nz), shift=tuple(steps * c[k]), axis=(0, 1, 2)).ravel()
+            assert np.array_equal(got[k], want), (scheme, steps, k)
+
+
+def push_bounce_back(cfg, c, t, opp, fl, f, u_lid):
+    """Push-form brute force of one streaming step with identity collision:
+    population k of fluid cell x moves to x + c_k; if that cell is a wall it
+    returns to x in direction kbar, picking up -6 t_k c_k . u_w."""
+    nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
+    new = f.copy()
+    for x, y, z in itertools.product(range(nx), range(ny), range(nz)):
+        i = (x * ny + y) * nz + z
+        if fl[i] != 0:
+            continue
+        for k in range(cfg.q):
+            if not c[k].any():
+                continue
+            d = ((x + c[k, 0]) * ny + (y + c[k, 1])) * nz + (z + c[k, 2])
+            if fl[d] == 0:
+                new[k, d] = f[k, i]
+            else:
+                uw = np.array(u_lid) if fl[d] == 2 else np.zeros(3)
+                new[opp[k], i] = f[k, i] - 6 * t[k] * (c[k] @ uw)
+    return new
+
+
+@pytest.mark.parametrize("q", (19, 27))
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("u_lid", [(0.0, 0.0, 0.0), (0.07, 0.0, 0.0)])
+def test_cavity_bounce_back_brute_force(orc, q, scheme, u_lid):
+    nx, ny, nz = 5, 4, 6
+    cfg = orc.Config(q=q, nx=nx, ny=ny, nz=nz, omega=0.0, u_lid=u_lid)
+    c, t, opp = orc.lattice(q)
+    sim = orc.Simulation(cfg, scheme)
+    fl = sim.flags
+    f = sim.populations()
+    rnd = W.random_populations(43, q, cfg.ntot).T
+    f[:, fl == 0] = rnd[:, fl == 0]
+    sim.pop[:] = f.ravel()
+    if sim.out is not None:
+        sim.out[:] = sim.pop
+    for _ in range(2):
+        want = push_bounce_back(cfg, c, t, opp, fl, f, u_lid)
+        sim.step(1)
+        got = sim.populations()
+        assert np.abs(got - want).max() < 1e-16
+        if not any(u_lid):   # a pure permutation of the fluid values
+            assert np.array_equal(np.sort(got[:, fl == 0].ravel()), np.sort(f[:, fl == 0].ravel()))
+        f = want
+
+
+@pytest.mark.parametrize("q", (19, 27))
+@pytest.mark.parametrize("model", ("bgk", "trt", "reg", "rr"))
+def test_closed_cavity_conserves_mass(orc, q, model):
+    cfg = orc.Config(q=q, nx=7, ny=6, nz=8, model=orc.MODELS[model], omega=1.6, u_lid=(0.08, 0.0, 0.0))
+    sim = orc.Simulation(cfg, "ref")
+    m0, _ = sim.invariants()
+    sim.step(60)
+    m1, ke = sim.invariants()
+    assert abs(m1 - m0) < 1e-12 * m0
+    assert ke > 0.0
+
+
+def test_periodic_box_conserves_momentum(orc):
+    cfg = orc.Config(q=19, nx=6, ny=5, nz=4, geometry=orc.PERIODIC, model=orc.TRT, omega=1.2)
+    u = W.random_velocity(47, cfg.ntot, amp=0.05).T
+    sim = orc.Simulation(cfg, "aa", u=u)
+    def momentum():
+        rho, v = sim.macroscopic()
+        return (rho * v).sum(axis=1)
+    p0 = momentum()
+    sim.step(10)
+    assert np.abs(momentum() - p0).max() < 1e-14
+
+
+CASES = [
+    (19, g, m) for g in ("cavity", "periodic", "channel") for m in ("bgk", "trt", "reg", "rr")
+] + [(27, g, m) for g in ("cavity", "periodic") for m in ("bgk", "rr")]
+
+
+@pytest.mark.parametrize("q,geom,model", CASES)
+def test_schemes_and_layouts_agree_bit_exactly(orc, q, geom, model):
+    """Sec. 2.3: the six strategies (three schemes x two layouts) produce
+    identical results; checked after odd and even step counts."""
+    gid = {"cavity": orc.CAVITY, "periodic": orc.PERIODIC, "channel": orc.CHANNEL}[geom]
+    base = dict(q=q, nx=6, ny=5, nz=7, geometry=gid, model=orc.MODELS[model], omega=1.71,
+                omega_bulk=1.2 if model in ("reg", "rr") else None, u_lid=(0.05, 0.01, 0.0))
+    u0 = W.random_velocity(53, 6 * 5 * 7, amp=0.04).T
+    ref = orc.Simulation(orc.Config(**base), "ref", u=u0)
+    ref.step(3)
+    r3 = ref.populations()
+    ref.step(1)
+    r4 = ref.populations()
+    for layout in (orc.SOA, orc.AOS):
+        for scheme in ("2pop", "swap", "aa"):
+            sim = orc.Simulation(orc.Config(layout=layout, **base), scheme, u=u0)
+            sim.step(3)
+            assert np.array_equal(sim.populations(), r3), (layout, scheme, 3)
+            sim.step(1)
+            assert np.array_equal(sim.populations(), r4), (layout, scheme, 4)
+
+
+@pytest.mark.parametrize("scheme", ("2pop", "swap", "aa"))
+def test_traversal_order_does_not_matter(orc, scheme):
+    """Thread safety by order independence (Sec. 2.3): a random cell order
+    gives bit-identical populations."""
+    cfg = orc.Config(q=19, nx=7, ny=6, nz=5, model=orc.TRT, omega=1.8, u_lid=(0.06, 0.0, 0.0))
+    a = orc.Simulation(cfg, scheme)
+    b = orc.Simulation(cfg, scheme, order=W.shuffled_order(59, cfg.ntot))
+    a.step(5)
+    b.step(5)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def test_neighbour_index_convention(orc):
+    """Linear index i = (x*ny + y)*nz + z with z fastest (Sec. 2.5)."""
+    cfg = orc.Config(q=19, nx=4, ny=5, nz=6, geometry=orc.PERIODIC)
+    c, _, _ = orc.lattice(19)
+    for i in (0, 37, 119):
+        x, y, z = i // 30, (i % 30) // 6, i % 6
+        for k in range(19):
+            xx, yy, zz = (x + c[k, 0]) % 4, (y + c[k, 1]) % 5, (z + c[k, 2]) % 6
+            assert orc.neighbour_index(cfg, i, k) == (xx * 5 + yy) * 6 + zz
+
+
+def test_flags_of_the_cavity(orc):
+    cfg = orc.Config(q=19, nx=5, ny=4, nz=6)
+    fl = orc.flags(cfg).reshape(5, 4, 6)
+    assert (fl[1:-1, 1:-1, 1:-1] == 0).all()
+    assert (fl[:, :, -1] == 2).all()
+    shell = np.ones_like(fl, bool)
+    shell[1:-1, 1:-1, 1:-1] = False
+    shell[:, :, -1] = False
+    assert (fl[shell] == 1).all()
