@@ -1,0 +1,214 @@
+"""Benchmark of the lattice Boltzmann collide-and-stream step on one MI355X.
+
+Workload: D3Q19 lid-driven cavity 256^3 (wall layer included; Re = 1000,
+u_lid = 0.05), synthetic state at rest, populations resident in HBM. A step
+is one full time step of the method (gather, decode, moments, collision,
+encode, stream with bounce-back) over the whole lattice.
+
+Headline: FP64 storage, BGK, AA-pattern SoA (MLUPS over fluid cells). The
+same JSON line carries the FP32-shifted run of the same workload, the nine
+FP64 scheme x collision combinations, the measured copy-kernel bandwidth,
+the roofline of the dominant kernel and the CPU oracle baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2010_11751_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(key: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if recorded for
+    the current kernel sources (profiles/hbm_traffic.md)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    src = kernel_source_hash()
+    for line in open(path):
+        m = re.match(r"\|\s*" + re.escape(key) + r"\s*\|\s*([0-9a-f]+)\s*\|\s*([0-9.eE+]+)\s*\|", line)
+        if m and m.group(1) == src:
+            return float(m.group(2))
+    return None
+
+
+def time_steps(sim, steps: int, warmup: int):
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall  # ms per step (events), wall seconds
+
+
+def copy_ceiling_gbs(nbytes: int = 2 << 30, reps: int = 20) -> float:
+    import torch
+    from paper_2010_11751_amd import lbm
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    lbm.device_copy(b, a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lbm.device_copy(b, a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def run_case(scheme, coll, dtype, steps, warmup, cav):
+    from paper_2010_11751_amd import lbm
+    sim = lbm.Lattice(19, cav.n, scheme=scheme, collision=coll, omega=cav.omega, u_lid=cav.u_lid, dtype=dtype)
+    info = sim.info()
+    ms, wall = time_steps(sim, steps, warmup)
+    m, e = sim.invariants()
+    sim.close()
+    fluid = info.fluid_cells
+    launches = 2 if scheme == "swap" else 1
+    return {
+        "scheme": scheme, "collision": coll, "dtype": dtype,
+        "ms_per_step": ms, "wall_s": wall,
+        "mlups": fluid / (ms * 1e-3) / 1e6,
+        "mlups_all_cells": info.ntot / (ms * 1e-3) / 1e6,
+        "bytes_per_update": info.bytes_per_update,
+        "algorithmic_gbs": fluid * info.bytes_per_update / (ms * 1e-3) / 1e9,
+        "kernel_avg_ms": ms / launches,
+        "fluid_cells": fluid,
+        "finite": bool(m == m and e == e),
+        "block_size": info.block_size,
+    }
+
+
+def cpu_baseline(cav, budget_s: float = 12.0, max_steps: int = 20):
+    """The FP64 oracle (2Pop, BGK) on the host cores, on the same 256^3
+    cavity, timed over as many whole steps as fit in about budget_s."""
+    import numpy as np
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cfg = O.Config(q=19, nx=cav.n, ny=cav.n, nz=cav.n, model=O.BGK, omega=cav.omega, u_lid=(cav.u_lid, 0, 0))
+    sim = O.Simulation(cfg, "2pop")
+    sim.step(1)  # first touch of the pages
+    n, t0 = 0, time.perf_counter()
+    while n < max_steps and (time.perf_counter() - t0) < budget_s:
+        sim.step(1)
+        n += 1
+    dt = time.perf_counter() - t0
+    mlups = cav.fluid_cells * n / dt / 1e6
+    del sim
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n} whole 2Pop BGK FP64 steps of the 256^3 cavity ({dt:.1f} s), OpenMP over cells"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the nine FP64 scheme x collision runs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the cavity step runs on a single MI355X; "
+              "multi-GPU slab decomposition is not built (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2010_11751_amd import workloads as W
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    cav = W.CAVITY_256
+    print(f"# device: {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
+
+    head = run_case("aa", "bgk", "f64", args.steps, args.warmup, cav)
+    print(f"# f64 aa bgk: {head['mlups']:.0f} MLUPS, {head['algorithmic_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+    f32 = run_case("aa", "bgk", "f32", args.steps, args.warmup, cav)
+    print(f"# f32 aa bgk: {f32['mlups']:.0f} MLUPS, {f32['algorithmic_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+    sweep = []
+    if not args.no_sweep:
+        for scheme in ("2pop", "swap", "aa"):
+            for coll in ("bgk", "trt", "reg"):
+                r = run_case(scheme, coll, "f64", max(args.steps // 5, 20), max(args.warmup // 5, 10), cav)
+                sweep.append({k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()
+                              if k in ("scheme", "collision", "mlups", "algorithmic_gbs", "ms_per_step")})
+                print(f"# sweep {scheme} {coll}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    copy_gbs = copy_ceiling_gbs()
+    print(f"# copy kernel: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+
+    def roofline(r, key):
+        achieved = r["fluid_cells"] * r["bytes_per_update"] / (r["kernel_avg_ms"] * 1e-3) / 1e9
+        traffic = stored_traffic(key)
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "kernel": "k_step<19,BGK," + r["dtype"] + ",SoA,AA even/odd>",
+                "bytes_per_launch": r["fluid_cells"] * r["bytes_per_update"],
+                "frac_of_copy": round(achieved / copy_gbs, 4)}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(cav)
+        print(f"# cpu oracle: {cpu['value']} MLUPS on {cpu['cores']} threads", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "MLUPS + HBM GB/s vs peak, D3Q19 256^3 cavity: FP64 vs FP32-shifted storage",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "D3Q19 lid-driven cavity 256^3 incl. walls, Re=1000, u_lid=0.05, "
+                               "BGK, AA-pattern SoA, FP64 populations",
+                   "cells": cav.cells, "fluid_cells": cav.fluid_cells, "omega": round(cav.omega, 6),
+                   "parallelism": "single GPU"},
+        "hbm_gbs": round(head["algorithmic_gbs"], 1),
+        "roofline": roofline(head, "aa_bgk_f64_256"),
+        "fp32_shifted": {"value": round(f32["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(f32["ms_per_step"], 5),
+                         "hbm_gbs": round(f32["algorithmic_gbs"], 1), "speedup_vs_f64": round(f32["mlups"] / head["mlups"], 3),
+                         "roofline": roofline(f32, "aa_bgk_f32_256")},
+        "copy_kernel_gbs": round(copy_gbs, 1),
+        "sweep_f64": sweep,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

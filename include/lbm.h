@@ -1,0 +1,225 @@
+/*
+ * lbm.h - C ABI of the MI355X lattice Boltzmann collide-and-stream library.
+ *
+ * The library advances a 3-D lattice Boltzmann simulation (D3Q19 or D3Q27)
+ * by the fused collide-and-stream time step of Latt, Coreixas & Beny,
+ * "Cross-platform programming model for many-core lattice Boltzmann
+ * simulation" (arXiv:2010.11751):
+ *   - collision  f_out_k(x) = Omega_k(f(x))        (Sec. 2.1, Eq. collision_step)
+ *   - streaming  f_k(x + c_k, t+1) = f_out_k(x, t)  (Sec. 2.1)
+ *   - half-way bounce-back with momentum exchange   (Sec. 2.1, Eq. momentum-exchange)
+ *     f_kbar(x, t+1) = f_out_k(x, t) - 6 t_k rho_w c_k . u_w, rho_w = 1,
+ *     wall cells storing the precomputed term        (Eqs. storage1, storage2)
+ *   - memory-access schemes 2Pop / swap / AA        (Sec. 2.3, Table 1)
+ *   - layouts SoA pop[k][N] and AoS pop[N][Q]       (Sec. 2.3)
+ *   - collision models BGK, TRT, regularized, recursive regularized (Sec. 2.2),
+ *     with the bulk-viscosity knob of Sec. 2.6 (Eq. bulk).
+ * The handle plays the role of the paper's stateless per-cell operator over
+ * a lattice pointer, velocities, weights, omega and dimensions (Sec. 2.5).
+ *
+ * Conventions
+ *   - Cell (x, y, z) has linear index i = (x*ny + y)*nz + z (z fastest), as
+ *     in Sec. 2.5; Ntot = nx*ny*nz; every index is 64-bit safe.
+ *   - Velocity order (D3Q19): k = 0..8 are (-1,0,0) (0,-1,0) (0,0,-1)
+ *     (-1,-1,0) (-1,0,-1) (-1,0,1) (-1,1,0) (0,-1,-1) (0,-1,1); k = 9 is rest;
+ *     c_{k+10} = -c_k. D3Q27: k = 0..12 are the same nine followed by
+ *     (-1,-1,-1) (-1,-1,1) (-1,1,-1) (-1,1,1); k = 13 is rest; c_{k+14} = -c_k.
+ *     This order has c_0 = (-1,0,0) = -c_10 as in the worked example of Sec. 2.6.
+ *   - "Natural populations" f[k][Ntot] (FP64) are the pre-collision values of
+ *     Eq. storage1 in every fluid cell and the stored momentum-exchange terms
+ *     in wall cells, whatever the scheme, layout, AA phase or storage type.
+ *   - Flags (uint8): LBM_FLUID, LBM_WALL, LBM_LID. Cavity geometry: fluid
+ *     inside, one wall layer on each face, the whole z = nz-1 layer is the lid
+ *     moving with lid_velocity. Periodic: all fluid, all axes wrap. Channel:
+ *     x and y wrap, wall at z = 0, lid at z = nz-1.
+ *   - Pointers are device pointers unless lbm_desc.ptr_kind = LBM_PTR_HOST.
+ *   - Every call is ordered on the handle's stream; calls that return data to
+ *     the caller (macroscopic, populations, flags, invariants) wait for it.
+ *   - A handle is not thread safe. Errors: negative return codes, NULL
+ *     handles; lbm_last_error() gives the thread's last message.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum lbm_status {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,       /* bad argument (message in lbm_last_error)        */
+    LBM_ENOMEM = -2,       /* device allocation failed                        */
+    LBM_EDEVICE = -3,      /* HIP runtime error (HIP message attached)        */
+    LBM_ENONFINITE = -4,   /* invariant monitor found NaN/Inf                 */
+    LBM_EUNSUPPORTED = -5  /* valid but unsupported combination               */
+};
+enum lbm_scheme { LBM_2POP = 0, LBM_SWAP = 1, LBM_AA = 2 };
+enum lbm_collision { LBM_BGK = 0, LBM_TRT = 1, LBM_REG = 2, LBM_RR = 3 };
+enum lbm_dtype { LBM_F64 = 0, LBM_F32_SHIFTED = 1, LBM_F16_SHIFTED = 2 };
+enum lbm_layout { LBM_SOA = 0, LBM_AOS = 1 };
+enum lbm_geometry { LBM_CAVITY = 0, LBM_PERIODIC = 1, LBM_CHANNEL = 2 };
+enum lbm_flag { LBM_FLUID = 0, LBM_WALL = 1, LBM_LID = 2 };
+enum lbm_ptr_kind { LBM_PTR_DEVICE = 0, LBM_PTR_HOST = 1 };
+
+typedef struct lbm_handle lbm_handle;
+typedef struct lbm_batch lbm_batch;
+
+/* Full description of a simulation. Fill with lbm_desc_default() first. */
+typedef struct lbm_desc {
+    int lattice;          /* 19 or 27                                          */
+    int nx, ny, nz;       /* box size, wall layers included                    */
+    int scheme;           /* lbm_scheme                                        */
+    int collision;        /* lbm_collision                                     */
+    int storage_dtype;    /* lbm_dtype: FP64, or shifted g = f - t_k in FP32/FP16 */
+    int layout;           /* lbm_layout                                        */
+    int geometry;         /* lbm_geometry                                      */
+    int ptr_kind;         /* lbm_ptr_kind of the data pointers of later calls  */
+    int check_every;      /* >0: invariant monitor every so many steps         */
+    int block_size;       /* threads per block of the step kernels; 0 = auto   */
+    double omega;         /* shear relaxation frequency, 0 < omega < 2         */
+    double trt_lambda;    /* TRT magic parameter (default 1/4)                 */
+    double omega_bulk;    /* bulk relaxation of REG/RR; <= 0 means = omega     */
+    double lid_velocity[3]; /* u_w of LID cells, |u_w| < 0.4                   */
+    void *stream;         /* hipStream_t; NULL = the null stream               */
+    void *pop;            /* optional caller-owned device buffers (see         */
+    void *out;            /*   lbm_required_bytes); caller keeps ownership and */
+    void *flags;          /*   must keep them alive until lbm_destroy          */
+} lbm_desc;
+
+/* Per-handle facts for reporting. */
+typedef struct lbm_info {
+    int64_t ntot;             /* cells                                         */
+    int64_t fluid_cells;      /* cells updated per step                        */
+    int64_t pop_stride;       /* SoA elements between populations              */
+    int64_t steps_done;       /* steps advanced since creation / last set      */
+    int64_t first_nonfinite;  /* step at which the monitor tripped, else -1    */
+    int64_t bytes_per_update; /* algorithmic HBM bytes per fluid-cell update    */
+    int aa_phase;             /* AA: 1 if the next step is odd                 */
+    int block_size;           /* block size the step kernels use               */
+} lbm_info;
+
+/* Fill d with defaults: D3Q19, 8^3 cavity, AA, BGK, FP64, SoA, omega 1,
+ * Lambda 1/4, omega_bulk = omega, lid at rest, device pointers. */
+void lbm_desc_default(lbm_desc *d);
+
+/* Bytes of the population array(s) and flag array the description needs:
+ * out[0] = pop, out[1] = out (0 unless 2Pop), out[2] = flags. Caller buffers
+ * must be at least this large and 256-byte aligned. Returns a status. */
+int lbm_required_bytes(const lbm_desc *d, size_t out[3]);
+
+/* Create a cavity simulation (Sec. 3.1 benchmark case): lid moving along +x
+ * at u_lid on the z = nz-1 layer; SoA; Lambda 1/4; omega_bulk = omega; null
+ * stream; library-owned buffers. Initialised to equilibrium rho = 1, u = 0.
+ * Returns NULL on error (see lbm_last_error). */
+lbm_handle *lbm_create(int lattice, int nx, int ny, int nz, int scheme, int collision,
+                       double omega, double u_lid, int storage_dtype);
+
+/* Create from a full description; same initial state as lbm_create. */
+lbm_handle *lbm_create_ex(const lbm_desc *d);
+
+/* Free library-owned buffers and the handle (caller buffers are untouched). */
+void lbm_destroy(lbm_handle *h);
+
+/* Set every fluid cell to the model's equilibrium E(rho, u) (Eq. storage1)
+ * and every wall cell to its momentum-exchange terms (Eq. storage2).
+ * rho[Ntot] and u[3][Ntot] (SoA) may be NULL (rho = 1, u = 0). Resets the
+ * AA phase and the step counter. */
+int lbm_init_equilibrium(lbm_handle *h, const double *rho, const double *u);
+
+/* Advance n >= 0 time steps (asynchronous on the handle's stream unless the
+ * invariant monitor is on). AA phase is tracked, so any n is allowed.
+ * Returns LBM_ENONFINITE if the monitor finds a non-finite mass or energy. */
+int lbm_step(lbm_handle *h, int n);
+
+/* Density rho[Ntot] and velocity u[3][Ntot] (FP64) of the natural state;
+ * wall cells get rho = 0, u = 0. */
+int lbm_macroscopic(lbm_handle *h, double *rho, double *u);
+
+/* Natural populations f[k][Ntot] (FP64), decoded from the storage type. */
+int lbm_get_populations(lbm_handle *h, double *f);
+
+/* Natural populations of the listed cells only: f[j*Q + k] for cells[j],
+ * j < n (FP64), so that large lattices can be checked on samples. Both
+ * arrays follow ptr_kind; indices must lie in [0, Ntot). */
+int lbm_get_populations_at(lbm_handle *h, const int64_t *cells, int n, double *f);
+
+/* Load natural populations f[k][Ntot] (FP64) into fluid cells (wall-cell
+ * entries are ignored: wall terms are fixed by the geometry). Encodes to the
+ * storage type (round to nearest even), resets the AA phase to even. */
+int lbm_set_populations(lbm_handle *h, const double *f);
+
+/* Cell flags (LBM_FLUID / LBM_WALL / LBM_LID), flags[Ntot]. */
+int lbm_get_flags(lbm_handle *h, uint8_t *flags);
+
+/* Global mass sum_fluid sum_k f_k and kinetic energy 1/2 sum_fluid rho|u|^2
+ * of the natural state, reduced in FP64 in a fixed order (host pointers). */
+int lbm_invariants(lbm_handle *h, double *mass, double *kinetic_energy);
+
+/* Linear index of the neighbour x + c_k of each listed cell, as the step
+ * kernels compute it (wrapping on periodic axes): out[j*Q + k] for
+ * cells[j], j < n. Both arrays follow ptr_kind. */
+int lbm_neighbor_index(lbm_handle *h, const int64_t *cells, int n, int64_t *out);
+
+/* Facts about the handle (host pointer). */
+int lbm_get_info(lbm_handle *h, lbm_info *info);
+
+/* Velocity table c[Q][3], weights t[Q], opposites opp[Q] of the kernels
+ * (host pointers; no device needed). */
+int lbm_lattice(int lattice, int32_t *c, double *t, int32_t *opp);
+
+/* Plain device-to-device copy of `bytes` (multiple of 16, 16-byte aligned
+ * pointers) by a streaming kernel on `stream` (hipStream_t, may be NULL).
+ * Not part of the method: it measures the attainable HBM bandwidth that the
+ * step kernels are compared with, and calibrates hardware byte counters. */
+int lbm_device_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* Wait for all work queued on the handle's stream. */
+int lbm_sync(lbm_handle *h);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *lbm_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Batched ensemble: many independent cubic or box cavities of uneven sizes
+ * and relaxation frequencies advanced together, one kernel launch per time
+ * step over a (cavity, tile) work table; the step loop can be captured in a
+ * HIP graph. Each cavity is the same problem as lbm_create's. */
+
+typedef struct lbm_cavity_desc {
+    int nx, ny, nz;       /* wall layers included                              */
+    double omega;         /* shear relaxation frequency                        */
+    double u_lid;         /* lid speed along +x on the z = nz-1 layer          */
+    double trt_lambda;    /* TRT magic parameter (<= 0: 1/4)                   */
+} lbm_cavity_desc;
+
+typedef struct lbm_batch_opts {
+    int use_graph;        /* capture the step loop in a HIP graph              */
+    int graph_steps;      /* steps per captured graph (even, default 100)      */
+    int autotune;         /* time candidate block sizes on first step          */
+    int block_size;       /* fixed block size when autotune = 0 (0 = 256)      */
+    void *stream;         /* hipStream_t; NULL = a library-owned stream        */
+} lbm_batch_opts;
+
+/* Create count cavities (FP64 or shifted FP32/FP16, D3Q19, any scheme but
+ * swap, any collision). opts may be NULL. Initial state: rho = 1, u = 0. */
+lbm_batch *lbm_batch_create(int count, const lbm_cavity_desc *d, int scheme, int collision,
+                            int storage_dtype, const lbm_batch_opts *opts);
+int lbm_batch_step(lbm_batch *b, int n);
+/* Same n steps, one kernel launch per cavity per step (reference timing). */
+int lbm_batch_step_sequential(lbm_batch *b, int n);
+int lbm_batch_macroscopic(lbm_batch *b, int idx, double *rho, double *u);
+int lbm_batch_get_populations(lbm_batch *b, int idx, double *f);
+/* FP64 mass and kinetic energy of every cavity: mass[count], ke[count] (host). */
+int lbm_batch_invariants(lbm_batch *b, double *mass, double *kinetic_energy);
+/* Total cells, fluid cells and block size in use (host pointers). */
+int lbm_batch_info(lbm_batch *b, int64_t *cells, int64_t *fluid_cells, int *block_size);
+int lbm_batch_sync(lbm_batch *b);
+void lbm_batch_destroy(lbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

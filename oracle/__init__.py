@@ -94,6 +94,7 @@ def lib():
         L.oracle_collide.argtypes = [cfgp, P, P]
         L.oracle_init_state.argtypes = [cfgp, P, P, P, P]
         L.oracle_reference_step.argtypes = [cfgp, P, P, P]
+        L.oracle_reference_cells.argtypes = [cfgp, P, P, P, ctypes.c_int64, P]
         L.oracle_2pop_step.argtypes = [cfgp, P, P, P, P]
         L.oracle_swap_step.argtypes = [cfgp, P, P, P]
         L.oracle_aa_step.argtypes = [cfgp, P, P, ctypes.c_int, P]
@@ -159,6 +160,15 @@ def reference_step(cfg: Config, fl, f) -> np.ndarray:
     new = np.empty_like(f)
     _check(lib().oracle_reference_step(ctypes.byref(cfg.c_struct()), _p(fl), _p(f), _p(new)))
     return new
+
+
+def reference_cells(cfg: Config, fl, f, cells) -> np.ndarray:
+    """Reference-step populations of the listed cells only: out[j][k]."""
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.zeros((cells.size, cfg.q))
+    _check(lib().oracle_reference_cells(ctypes.byref(cfg.c_struct()), _p(fl), _p(f), _p(cells),
+                                        cells.size, _p(out)))
+    return out
 
 
 def twopop_step(cfg: Config, fl, pop, out, order=None) -> None:

@@ -468,6 +468,41 @@ int oracle_reference_step(const ocfg *g, const uint8_t *flags, const double *f, 
     return 0;
 }
 
+/* The reference step for a list of cells only: new populations of cell
+ * cells[j] written to fnew[j*Q + k]. Same definition as above, evaluated one
+ * cell at a time so that large lattices can be checked on samples. */
+int oracle_reference_cells(const ocfg *g, const uint8_t *flags, const double *f,
+                           const int64_t *cells, int64_t ncells, double *fnew)
+{
+    olat L;
+    int64_t j;
+    if (make_lattice(g->q, &L)) return -1;
+    for (j = 0; j < ncells; ++j) {
+        int64_t i = cells[j];
+        double cell[27], out[27], own[27];
+        int k, m;
+        if (flags[i] != O_FLUID) {
+            for (k = 0; k < L.q; ++k) fnew[j * L.q + k] = f[at(g, i, k)];
+            continue;
+        }
+        for (m = 0; m < L.q; ++m) cell[m] = f[at(g, i, m)];
+        collide(&L, g, cell, own);
+        for (k = 0; k < L.q; ++k) {
+            int64_t s;
+            if (k == L.rest) { fnew[j * L.q + k] = own[k]; continue; }
+            s = neighbour(g, i, L.c[k], -1);
+            if (flags[s] == O_FLUID) {
+                for (m = 0; m < L.q; ++m) cell[m] = f[at(g, s, m)];
+                collide(&L, g, cell, out);
+                fnew[j * L.q + k] = out[k];
+            } else {
+                fnew[j * L.q + k] = own[L.opp[k]] + wall_term(&L, g, flags[s], L.opp[k]);
+            }
+        }
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* The three memory-access schemes of Table 1, executed on fluid cells in the
  * order given by `order` (a permutation of 0..Ntot-1; NULL = natural order).

@@ -1,0 +1,83 @@
+// Launch dispatcher of one (Q, storage) kernel translation unit: maps the
+// runtime model / layout / kind of a Launch onto kernel instantiations.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace lbm {
+
+template <int Q, int MODEL, class ST, int LAYOUT>
+hipError_t launch_step_kind(const Launch& L, hipStream_t s)
+{
+    const dim3 g(L.grid), b(L.block);
+    switch (L.kind) {
+    case KIND_2POP: k_step<Q, MODEL, ST, LAYOUT, KIND_2POP><<<g, b, 0, s>>>(L.F, L.relax); break;
+    case KIND_SWAP_COLLIDE: k_step<Q, MODEL, ST, LAYOUT, KIND_SWAP_COLLIDE><<<g, b, 0, s>>>(L.F, L.relax); break;
+    case KIND_SWAP_STREAM: k_step<Q, BGK, ST, LAYOUT, KIND_SWAP_STREAM><<<g, b, 0, s>>>(L.F, L.relax); break;
+    case KIND_AA_EVEN: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_EVEN><<<g, b, 0, s>>>(L.F, L.relax); break;
+    case KIND_AA_ODD: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, 0, s>>>(L.F, L.relax); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int Q, int MODEL, class ST, int LAYOUT>
+hipError_t launch_batch_kind(const Launch& L, hipStream_t s)
+{
+    const dim3 g(L.grid), b(L.block);
+    switch (L.kind) {
+    case KIND_2POP: k_step_batch<Q, MODEL, ST, LAYOUT, KIND_2POP><<<g, b, 0, s>>>(L.cav, L.tiles); break;
+    case KIND_AA_EVEN: k_step_batch<Q, MODEL, ST, LAYOUT, KIND_AA_EVEN><<<g, b, 0, s>>>(L.cav, L.tiles); break;
+    case KIND_AA_ODD: k_step_batch<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, 0, s>>>(L.cav, L.tiles); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int Q, class ST, int LAYOUT, int MODEL>
+hipError_t launch_model(const Launch& L, hipStream_t s)
+{
+    const dim3 g(L.grid), b(L.block);
+    switch (L.op) {
+    case OP_STEP: return launch_step_kind<Q, MODEL, ST, LAYOUT>(L, s);
+    case OP_STEP_BATCH:
+        if constexpr (Q == 19 && LAYOUT == LAYOUT_SOA) return launch_batch_kind<Q, MODEL, ST, LAYOUT>(L, s);
+        else return hipErrorInvalidValue;
+    case OP_INIT: k_init<Q, MODEL, ST, LAYOUT><<<g, b, 0, s>>>(L.F, L.init); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int Q, class ST, int LAYOUT>
+hipError_t launch_layout(const Launch& L, hipStream_t s)
+{
+    const dim3 g(L.grid), b(L.block);
+    switch (L.op) {
+    case OP_GET: k_get_populations<Q, ST, LAYOUT><<<g, b, 0, s>>>(L.F, L.aa_odd, L.d0); break;
+    case OP_MACRO: k_macroscopic<Q, ST, LAYOUT><<<g, b, 0, s>>>(L.F, L.aa_odd, L.d0, L.d1); break;
+    case OP_SET: k_set_populations<Q, ST, LAYOUT><<<g, b, 0, s>>>(L.F, L.c0); break;
+    case OP_INVARIANTS: k_invariants<Q, ST, LAYOUT><<<g, b, 0, s>>>(L.F, L.aa_odd, L.d0); break;
+    case OP_NEIGHBORS: k_neighbors<Q><<<g, b, 0, s>>>(L.F, L.cells, L.n, L.idx_out); break;
+    case OP_GET_CELLS: k_get_cells<Q, ST, LAYOUT><<<g, b, 0, s>>>(L.F, L.aa_odd, L.cells, L.n, L.d0); break;
+    default:
+        switch (L.model) {
+        case BGK: return launch_model<Q, ST, LAYOUT, BGK>(L, s);
+        case TRT: return launch_model<Q, ST, LAYOUT, TRT>(L, s);
+        case REG: return launch_model<Q, ST, LAYOUT, REG>(L, s);
+        case RR: return launch_model<Q, ST, LAYOUT, RR>(L, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+template <int Q, class ST>
+hipError_t launch_tu(const Launch& L, hipStream_t s)
+{
+    if (L.layout == LAYOUT_SOA) return launch_layout<Q, ST, LAYOUT_SOA>(L, s);
+    if (L.layout == LAYOUT_AOS) return launch_layout<Q, ST, LAYOUT_AOS>(L, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

@@ -1,0 +1,97 @@
+// Types shared by the host runtime and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbm {
+
+// Flag byte: cell type in bits 0-1, fast-path hints in bits 6-7.
+enum : uint8_t {
+    FL_TYPE = 0x03,
+    FL_FLUID = 0,
+    FL_WALL = 1,
+    FL_LID = 2,
+    FL_BORDER = 0x40,    // fluid cell on a box face: neighbours may wrap
+    FL_NEARWALL = 0x80,  // fluid cell with at least one non-fluid neighbour
+    FL_SLOW = FL_BORDER | FL_NEARWALL,
+};
+
+enum Layout { LAYOUT_SOA = 0, LAYOUT_AOS = 1 };
+enum Kind { KIND_2POP = 0, KIND_SWAP_COLLIDE = 1, KIND_SWAP_STREAM = 2, KIND_AA_EVEN = 3, KIND_AA_ODD = 4 };
+enum Storage { STORE_F64 = 0, STORE_F32 = 1, STORE_F16 = 2 };
+
+struct StoreF64 {
+    using T = double;
+    using R = double;
+    static constexpr bool shifted = false;
+};
+struct StoreF32 {
+    using T = float;
+    using R = float;
+    static constexpr bool shifted = true;
+};
+struct StoreF16 {
+    using T = _Float16;
+    using R = float;
+    static constexpr bool shifted = true;
+};
+
+// One lattice as the kernels see it.
+struct Field {
+    void* pop;
+    void* out;             // 2Pop destination (null otherwise)
+    const uint8_t* flags;
+    int64_t stride;        // SoA elements between populations
+    uint32_t ntot;
+    int nx, ny, nz;
+};
+
+struct RelaxD {
+    double omega, omega_m, omega_b;
+};
+
+struct InitArgs {
+    const double* rho;     // device, may be null
+    const double* u;       // device [3][ntot], may be null
+    double lid[3];
+};
+
+struct BatchCavity {
+    Field F;
+    RelaxD relax;
+};
+
+// A launch request handled by the kernel translation unit of (Q, storage).
+enum Op { OP_STEP = 0, OP_GET = 1, OP_MACRO = 2, OP_SET = 3, OP_INIT = 4, OP_INVARIANTS = 5, OP_NEIGHBORS = 6,
+          OP_STEP_BATCH = 7, OP_GET_CELLS = 8 };
+
+struct Launch {
+    int op;
+    int model, layout, kind;
+    int aa_odd;
+    int block;
+    uint32_t grid;
+    Field F;
+    RelaxD relax;
+    InitArgs init;
+    double* d0;            // GET: f; MACRO: rho; INVARIANTS: partials
+    double* d1;            // MACRO: u
+    const double* c0;      // SET: f
+    const int64_t* cells;  // NEIGHBORS
+    int64_t* idx_out;
+    int n;
+    const BatchCavity* cav;  // STEP_BATCH
+    const uint32_t* tiles;
+};
+
+hipError_t launch_q19_f64(const Launch& L, hipStream_t s);
+hipError_t launch_q19_f32(const Launch& L, hipStream_t s);
+hipError_t launch_q19_f16(const Launch& L, hipStream_t s);
+hipError_t launch_q27_f64(const Launch& L, hipStream_t s);
+hipError_t launch_q27_f32(const Launch& L, hipStream_t s);
+hipError_t launch_q27_f16(const Launch& L, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,485 @@
+// Step, read-out and set-up kernels of the lattice Boltzmann library.
+//
+// One thread updates one cell; cells are numbered i = (x*ny + y)*nz + z
+// (Sec. 2.5), so a wavefront covers 64 consecutive z and every population
+// stream is read and written as contiguous runs (SoA). Flags carry the cell
+// type in bits 0-1 and two hints: FL_BORDER (fluid cell on a box face, whose
+// neighbours may wrap) and FL_NEARWALL (fluid cell with a non-fluid
+// neighbour). Cells without hints take the fast path: neighbour i + d_k, no
+// flag look-ups, no bounce-back branch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "collide.hpp"
+#include "internal.hpp"
+
+namespace lbm {
+
+template <class ST>
+using real_t = typename ST::R;
+
+template <class ST, int LAYOUT, int Q>
+struct Acc {
+    using T = typename ST::T;
+    T* base;
+    int64_t stride;
+    __device__ __forceinline__ T* ptr(uint32_t i, int k) const
+    {
+        if constexpr (LAYOUT == LAYOUT_SOA) return base + (size_t)k * (size_t)stride + i;
+        else return base + (size_t)i * Q + k;
+    }
+    __device__ __forceinline__ real_t<ST> ld(uint32_t i, int k) const { return real_t<ST>(*ptr(i, k)); }
+    __device__ __forceinline__ void st(uint32_t i, int k, real_t<ST> v) const { *ptr(i, k) = T(v); }
+};
+
+struct Coord {
+    int x, y, z;
+};
+
+__device__ __forceinline__ Coord cell_coord(uint32_t i, const Field& F)
+{
+    const uint32_t plane = (uint32_t)F.ny * (uint32_t)F.nz;
+    Coord c;
+    c.x = (int)(i / plane);
+    const uint32_t r = i - (uint32_t)c.x * plane;
+    c.y = (int)(r / (uint32_t)F.nz);
+    c.z = (int)(r - (uint32_t)c.y * (uint32_t)F.nz);
+    return c;
+}
+
+// Neighbour x + s*c_k. Interior cells: constant offset. Border cells: wrap
+// each coordinate (only periodic axes ever wrap for a fluid cell).
+template <int Q, int K, int SIGN>
+__device__ __forceinline__ uint32_t neighbour(const Field& F, uint32_t i, bool border, const Coord& c)
+{
+    constexpr int cx = SIGN * L<Q>::cx(K), cy = SIGN * L<Q>::cy(K), cz = SIGN * L<Q>::cz(K);
+    if (!border) return (uint32_t)((int64_t)i + (int64_t)cx * F.ny * F.nz + (int64_t)cy * F.nz + cz);
+    int x = c.x + cx, y = c.y + cy, z = c.z + cz;
+    x = x < 0 ? x + F.nx : (x >= F.nx ? x - F.nx : x);
+    y = y < 0 ? y + F.ny : (y >= F.ny ? y - F.ny : y);
+    z = z < 0 ? z + F.nz : (z >= F.nz ? z - F.nz : z);
+    return ((uint32_t)x * (uint32_t)F.ny + (uint32_t)y) * (uint32_t)F.nz + (uint32_t)z;
+}
+
+template <int Q, int K, int SIGN>
+__device__ __forceinline__ int32_t offset(const Field& F)
+{
+    constexpr int cx = SIGN * L<Q>::cx(K), cy = SIGN * L<Q>::cy(K), cz = SIGN * L<Q>::cz(K);
+    return cx * F.ny * F.nz + cy * F.nz + cz;
+}
+
+__device__ __forceinline__ bool is_fluid(const Field& F, uint32_t j) { return (F.flags[j] & FL_TYPE) == FL_FLUID; }
+
+template <class R>
+__device__ __forceinline__ Relax<R> relax_of(const RelaxD& p)
+{
+    return Relax<R>{R(p.omega), R(p.omega_m), R(p.omega_b)};
+}
+
+// ---------------------------------------------------------------------------
+// Double-population scheme (Table 1, row 2Pop): collide pop(x), push
+// out_k(x + c_k) <- f_out_k, or out_kbar(x) <- f_out_k + pop_k(x + c_k) when
+// the neighbour is a wall (whose pop_k holds the momentum-exchange term).
+template <int Q, int MODEL, class ST, int LAYOUT>
+__device__ __forceinline__ void cell_2pop(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    const uint8_t fl = F.flags[i];
+    if ((fl & FL_TYPE) != FL_FLUID) return;
+    const Acc<ST, LAYOUT, Q> src{(typename ST::T*)F.pop, F.stride};
+    const Acc<ST, LAYOUT, Q> dst{(typename ST::T*)F.out, F.stride};
+    R g[Q];
+    static_for<0, Q>([&](auto K) { g[K] = src.ld(i, K); });
+    collide<Q, MODEL, ST::shifted>(g, p);
+    if (!(fl & FL_SLOW)) {
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            dst.st((uint32_t)((int32_t)i + offset<Q, k, 1>(F)), k, g[k]);
+        });
+    } else {
+        const bool border = fl & FL_BORDER;
+        const Coord c = border ? cell_coord(i, F) : Coord{0, 0, 0};
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            if constexpr (k == S::rest) {
+                dst.st(i, k, g[k]);
+            } else {
+                const uint32_t j = neighbour<Q, k, 1>(F, i, border, c);
+                if (is_fluid(F, j)) dst.st(j, k, g[k]);
+                else dst.st(i, S::opp(k), g[k] + src.ld(j, k));
+            }
+        });
+    }
+}
+
+// Swap algorithm, collision sweep (Table 1, row Swap): pop_kbar(x) <- f_out_k.
+template <int Q, int MODEL, class ST, int LAYOUT>
+__device__ __forceinline__ void cell_swap_collide(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    if ((F.flags[i] & FL_TYPE) != FL_FLUID) return;
+    const Acc<ST, LAYOUT, Q> a{(typename ST::T*)F.pop, F.stride};
+    R g[Q];
+    static_for<0, Q>([&](auto K) { g[K] = a.ld(i, K); });
+    collide<Q, MODEL, ST::shifted>(g, p);
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        a.st(i, S::opp(k), g[k]);
+    });
+}
+
+// Swap algorithm, streaming sweep over k < rest: pop_kbar(x) <-> pop_k(x + c_k)
+// with a fluid neighbour, pop_kbar(x) += pop_k(x + c_k) with a wall one. The
+// wall cells' duty of the Table 1 caption (nb_pop_k += pop_kbar towards fluid
+// neighbours) is done here by the fluid cell: pop_k(x) += pop_kbar(x - c_k)
+// when x - c_k is a wall. Every location is touched by exactly one thread.
+template <int Q, class ST, int LAYOUT>
+__device__ __forceinline__ void cell_swap_stream(const Field& F, uint32_t i)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    const uint8_t fl = F.flags[i];
+    if ((fl & FL_TYPE) != FL_FLUID) return;
+    const Acc<ST, LAYOUT, Q> a{(typename ST::T*)F.pop, F.stride};
+    if (!(fl & FL_SLOW)) {
+        static_for<0, S::half>([&](auto K) {
+            constexpr int k = K;
+            const uint32_t j = (uint32_t)((int32_t)i + offset<Q, k, 1>(F));
+            const auto mine = *a.ptr(i, S::opp(k));
+            const auto theirs = *a.ptr(j, k);
+            *a.ptr(i, S::opp(k)) = theirs;
+            *a.ptr(j, k) = mine;
+        });
+    } else {
+        const bool border = fl & FL_BORDER;
+        const Coord c = border ? cell_coord(i, F) : Coord{0, 0, 0};
+        static_for<0, S::half>([&](auto K) {
+            constexpr int k = K;
+            const uint32_t j = neighbour<Q, k, 1>(F, i, border, c);
+            if (is_fluid(F, j)) {
+                const auto mine = *a.ptr(i, S::opp(k));
+                const auto theirs = *a.ptr(j, k);
+                *a.ptr(i, S::opp(k)) = theirs;
+                *a.ptr(j, k) = mine;
+            } else {
+                a.st(i, S::opp(k), a.ld(i, S::opp(k)) + a.ld(j, k));
+            }
+            const uint32_t s = neighbour<Q, k, -1>(F, i, border, c);
+            if (!is_fluid(F, s)) a.st(i, k, a.ld(i, k) + a.ld(s, S::opp(k)));
+        });
+    }
+}
+
+// AA-pattern, even step (Table 1, row AA/Even): purely local,
+// pop_kbar(x) <- f_out_k.
+template <int Q, int MODEL, class ST, int LAYOUT>
+__device__ __forceinline__ void cell_aa_even(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
+{
+    cell_swap_collide<Q, MODEL, ST, LAYOUT>(F, p, i);
+}
+
+// AA-pattern, odd step (Table 1, row AA/Odd). Pull: f_k(x) is at
+// pop_kbar(x - c_k), or pop_k(x) + pop_kbar(x - c_k) across a wall. Collide.
+// Push: pop_k(x + c_k) <- f_out_k, or pop_kbar(x) <- f_out_k + pop_k(x + c_k)
+// across a wall. A cell writes exactly the locations it read.
+template <int Q, int MODEL, class ST, int LAYOUT>
+__device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    const uint8_t fl = F.flags[i];
+    if ((fl & FL_TYPE) != FL_FLUID) return;
+    const Acc<ST, LAYOUT, Q> a{(typename ST::T*)F.pop, F.stride};
+    R g[Q];
+    if (!(fl & FL_SLOW)) {
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            if constexpr (k == S::rest) g[k] = a.ld(i, k);
+            else g[k] = a.ld((uint32_t)((int32_t)i + offset<Q, k, -1>(F)), S::opp(k));
+        });
+        collide<Q, MODEL, ST::shifted>(g, p);
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            a.st((uint32_t)((int32_t)i + offset<Q, k, 1>(F)), k, g[k]);
+        });
+    } else {
+        const bool border = fl & FL_BORDER;
+        const Coord c = border ? cell_coord(i, F) : Coord{0, 0, 0};
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            if constexpr (k == S::rest) {
+                g[k] = a.ld(i, k);
+            } else {
+                const uint32_t s = neighbour<Q, k, -1>(F, i, border, c);
+                if (is_fluid(F, s)) g[k] = a.ld(s, S::opp(k));
+                else g[k] = a.ld(i, k) + a.ld(s, S::opp(k));
+            }
+        });
+        collide<Q, MODEL, ST::shifted>(g, p);
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            if constexpr (k == S::rest) {
+                a.st(i, k, g[k]);
+            } else {
+                const uint32_t j = neighbour<Q, k, 1>(F, i, border, c);
+                if (is_fluid(F, j)) a.st(j, k, g[k]);
+                else a.st(i, S::opp(k), g[k] + a.ld(j, k));
+            }
+        });
+    }
+}
+
+template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
+__device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
+{
+    if constexpr (KIND == KIND_2POP) cell_2pop<Q, MODEL, ST, LAYOUT>(F, p, i);
+    else if constexpr (KIND == KIND_SWAP_COLLIDE) cell_swap_collide<Q, MODEL, ST, LAYOUT>(F, p, i);
+    else if constexpr (KIND == KIND_SWAP_STREAM) cell_swap_stream<Q, ST, LAYOUT>(F, i);
+    else if constexpr (KIND == KIND_AA_EVEN) cell_aa_even<Q, MODEL, ST, LAYOUT>(F, p, i);
+    else cell_aa_odd<Q, MODEL, ST, LAYOUT>(F, p, i);
+}
+
+template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
+__global__ void __launch_bounds__(1024) k_step(Field F, RelaxD pd)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F.ntot) return;
+    cell_step<Q, MODEL, ST, LAYOUT, KIND>(F, relax_of<real_t<ST>>(pd), i);
+}
+
+// ---------------------------------------------------------------------------
+// Batched ensemble: one launch over a table of (cavity, first cell) tiles.
+template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
+__global__ void __launch_bounds__(1024) k_step_batch(const BatchCavity* __restrict__ cav,
+                                                     const uint32_t* __restrict__ tiles)
+{
+    const uint32_t t = tiles[blockIdx.x];
+    const uint32_t c = t >> 16;  // cavity
+    const BatchCavity& B = cav[c];
+    const uint32_t i = (t & 0xffffu) * blockDim.x + threadIdx.x;
+    if (i >= B.F.ntot) return;
+    cell_step<Q, MODEL, ST, LAYOUT, KIND>(B.F, relax_of<real_t<ST>>(B.relax), i);
+}
+
+// ---------------------------------------------------------------------------
+// Read-outs. Natural pre-collision populations of one cell (FP64): after an
+// AA even step the odd-step pull is applied without collision; shifted
+// storage is decoded as f = g + t_k; wall cells return their stored terms.
+template <int Q, class ST, int LAYOUT>
+__device__ __forceinline__ void natural_cell(const Field& F, uint32_t i, int aa_odd, double (&f)[Q])
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    const Acc<ST, LAYOUT, Q> a{(typename ST::T*)F.pop, F.stride};
+    const uint8_t fl = F.flags[i];
+    if ((fl & FL_TYPE) != FL_FLUID) {
+        static_for<0, Q>([&](auto K) { f[K] = double(a.ld(i, K)); });
+        return;
+    }
+    const bool border = fl & FL_BORDER;
+    const Coord c = border ? cell_coord(i, F) : Coord{0, 0, 0};
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        R v;
+        if (!aa_odd || k == S::rest) {
+            v = a.ld(i, k);
+        } else {
+            const uint32_t s = neighbour<Q, k, -1>(F, i, border, c);
+            if (is_fluid(F, s)) v = a.ld(s, S::opp(k));
+            else v = a.ld(i, k) + a.ld(s, S::opp(k));
+        }
+        f[k] = ST::shifted ? double(v) + S::t(k) : double(v);
+    });
+}
+
+template <int Q, class ST, int LAYOUT>
+__global__ void k_get_populations(Field F, int aa_odd, double* __restrict__ out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F.ntot) return;
+    double f[Q];
+    natural_cell<Q, ST, LAYOUT>(F, i, aa_odd, f);
+    static_for<0, Q>([&](auto K) { out[(size_t)K * F.ntot + i] = f[K]; });
+}
+
+template <int Q, class ST, int LAYOUT>
+__global__ void k_get_cells(Field F, int aa_odd, const int64_t* __restrict__ cells, int n, double* __restrict__ out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int64_t c = cells[j];
+    if (c < 0 || c >= (int64_t)F.ntot) return;
+    double f[Q];
+    natural_cell<Q, ST, LAYOUT>(F, (uint32_t)c, aa_odd, f);
+    static_for<0, Q>([&](auto K) { out[(size_t)j * Q + K] = f[K]; });
+}
+
+template <int Q>
+__device__ __forceinline__ void density_velocity(const double (&f)[Q], double& rho, double (&u)[3])
+{
+    using S = L<Q>;
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        r += f[k];
+        static_for<0, 3>([&](auto D) {
+            constexpr int a = D;
+            if constexpr (S::c(k, a) == 1) j[a] += f[k];
+            else if constexpr (S::c(k, a) == -1) j[a] -= f[k];
+        });
+    });
+    rho = r;
+    u[0] = j[0] / r;
+    u[1] = j[1] / r;
+    u[2] = j[2] / r;
+}
+
+template <int Q, class ST, int LAYOUT>
+__global__ void k_macroscopic(Field F, int aa_odd, double* __restrict__ rho, double* __restrict__ u)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F.ntot) return;
+    if ((F.flags[i] & FL_TYPE) != FL_FLUID) {
+        rho[i] = 0.0;
+        u[i] = u[(size_t)F.ntot + i] = u[2 * (size_t)F.ntot + i] = 0.0;
+        return;
+    }
+    double f[Q], r, v[3];
+    natural_cell<Q, ST, LAYOUT>(F, i, aa_odd, f);
+    density_velocity<Q>(f, r, v);
+    rho[i] = r;
+    u[i] = v[0];
+    u[(size_t)F.ntot + i] = v[1];
+    u[2 * (size_t)F.ntot + i] = v[2];
+}
+
+// Load natural populations into fluid cells (natural slots, AA phase even).
+template <int Q, class ST, int LAYOUT>
+__global__ void k_set_populations(Field F, const double* __restrict__ f)
+{
+    using S = L<Q>;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F.ntot || (F.flags[i] & FL_TYPE) != FL_FLUID) return;
+    const Acc<ST, LAYOUT, Q> a{(typename ST::T*)F.pop, F.stride};
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        const double v = f[(size_t)k * F.ntot + i];
+        a.st(i, k, real_t<ST>(ST::shifted ? v - S::t(k) : v));
+    });
+}
+
+// Momentum-exchange term of a wall cell, w_k = -6 t_k c_k . u_w with rho_w = 1
+// (Eq. momentum-exchange, Eq. storage2); u_w = lid velocity on LID cells.
+template <int Q, int K>
+__device__ __forceinline__ double wall_term(uint8_t type, const double (&lid)[3])
+{
+    using S = L<Q>;
+    if (type != FL_LID) return 0.0;
+    const double cu = S::cx(K) * lid[0] + S::cy(K) * lid[1] + S::cz(K) * lid[2];
+    return -6.0 * S::t(K) * cu;
+}
+
+// Fluid cells: the model's equilibrium at (rho, u) (rho = 1, u = 0 when the
+// pointers are null). Wall cells: wall terms. Written to pop and, if not null,
+// to out.
+template <int Q, int MODEL, class ST, int LAYOUT>
+__global__ void k_init(Field F, InitArgs ia)
+{
+    using R = real_t<ST>;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F.ntot) return;
+    const uint8_t type = F.flags[i] & FL_TYPE;
+    R g[Q];
+    if (type != FL_FLUID) {
+        const double lid[3] = {ia.lid[0], ia.lid[1], ia.lid[2]};
+        static_for<0, Q>([&](auto K) { g[K] = R(wall_term<Q, K>(type, lid)); });
+    } else {
+        const R rho = ia.rho ? R(ia.rho[i]) : R(1);
+        R u[3] = {R(0), R(0), R(0)};
+        if (ia.u) {
+            u[0] = R(ia.u[i]);
+            u[1] = R(ia.u[(size_t)F.ntot + i]);
+            u[2] = R(ia.u[2 * (size_t)F.ntot + i]);
+        }
+        equilibrium<Q, MODEL, ST::shifted>(rho, u, g);
+    }
+    const Acc<ST, LAYOUT, Q> a{(typename ST::T*)F.pop, F.stride};
+    static_for<0, Q>([&](auto K) { a.st(i, K, g[K]); });
+    if (F.out) {
+        const Acc<ST, LAYOUT, Q> b{(typename ST::T*)F.out, F.stride};
+        static_for<0, Q>([&](auto K) { b.st(i, K, g[K]); });
+    }
+}
+
+// Global FP64 mass and kinetic energy: each block reduces its cells
+// (wavefront shuffles, then LDS) and writes one partial pair; a second
+// single-block pass sums the partials in index order.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int Q, class ST, int LAYOUT>
+__global__ void __launch_bounds__(256) k_invariants(Field F, int aa_odd, double* __restrict__ partial)
+{
+    __shared__ double sm[2][4];
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    double mass = 0.0, ke = 0.0;
+    if (i < F.ntot && (F.flags[i] & FL_TYPE) == FL_FLUID) {
+        double f[Q], r, v[3];
+        natural_cell<Q, ST, LAYOUT>(F, i, aa_odd, f);
+        density_velocity<Q>(f, r, v);
+        static_for<0, Q>([&](auto K) { mass += f[K]; });
+        ke = 0.5 * r * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    }
+    mass = wave_sum(mass);
+    ke = wave_sum(ke);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        sm[0][w] = mass;
+        sm[1][w] = ke;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0, e = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+            m += sm[0][k];
+            e += sm[1][k];
+        }
+        partial[2 * (size_t)blockIdx.x] = m;
+        partial[2 * (size_t)blockIdx.x + 1] = e;
+    }
+}
+
+template <int Q>
+__global__ void k_neighbors(Field F, const int64_t* __restrict__ cells, int n, int64_t* __restrict__ out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    if (cells[j] < 0 || cells[j] >= (int64_t)F.ntot) {
+        for (int k = 0; k < Q; ++k) out[(size_t)j * Q + k] = -1;
+        return;
+    }
+    const uint32_t i = (uint32_t)cells[j];
+    const bool border = F.flags[i] & FL_BORDER;
+    const Coord c = cell_coord(i, F);
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        uint32_t nb;
+        if (border || (F.flags[i] & FL_TYPE) != FL_FLUID) {
+            nb = neighbour<Q, k, 1>(F, i, true, c);
+        } else {
+            nb = (uint32_t)((int32_t)i + offset<Q, k, 1>(F));
+        }
+        out[(size_t)j * Q + k] = nb;
+    });
+}
+
+}  // namespace lbm

@@ -1,0 +1,735 @@
+// Host runtime and C ABI of the lattice Boltzmann library (include/lbm.h).
+//
+// A handle owns (or borrows) the population array(s) and the flag array,
+// keeps the AA phase and step counter, and enqueues kernels on its stream.
+// Every launch goes through the (Q, storage) translation unit that holds the
+// kernel instantiations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "lattice.hpp"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+thread_local std::string g_error;
+}
+
+namespace lbm_detail {
+int set_error(int code, const std::string& msg)
+{
+    g_error = msg;
+    return code;
+}
+}  // namespace lbm_detail
+
+namespace {
+
+int fail(int code, const std::string& msg)
+{
+    g_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+using LaunchFn = hipError_t (*)(const Launch&, hipStream_t);
+
+LaunchFn pick_tu(int q, int dtype)
+{
+    if (q == 19) return dtype == LBM_F64 ? launch_q19_f64 : dtype == LBM_F32_SHIFTED ? launch_q19_f32 : launch_q19_f16;
+    return dtype == LBM_F64 ? launch_q27_f64 : dtype == LBM_F32_SHIFTED ? launch_q27_f32 : launch_q27_f16;
+}
+
+size_t elem_bytes(int dtype) { return dtype == LBM_F64 ? 8 : dtype == LBM_F32_SHIFTED ? 4 : 2; }
+
+// SoA stride: the cell count rounded up to 1024 elements, so that every
+// population stream starts on a fresh 2-8 KiB boundary.
+int64_t soa_stride(int64_t ntot)
+{
+    const int64_t a = 1024;
+    int64_t s = (ntot + a - 1) / a * a;
+    if (const char* e = std::getenv("LBM_STRIDE_PAD")) s += std::atoll(e);
+    return s;
+}
+
+double trt_omega_minus(double omega, double lambda)
+{
+    return 1.0 / (0.5 + lambda / (1.0 / omega - 0.5));
+}
+
+// --- flag construction ------------------------------------------------------
+
+__global__ void k_flag_types(uint8_t* fl, int nx, int ny, int nz, int geometry)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = (uint64_t)nx * ny * nz;
+    if (i >= n) return;
+    const int z = (int)(i % nz), y = (int)((i / nz) % ny), x = (int)(i / ((uint64_t)ny * nz));
+    uint8_t t = FL_FLUID;
+    if (geometry == LBM_CAVITY) {
+        const bool inside = x >= 1 && x <= nx - 2 && y >= 1 && y <= ny - 2 && z >= 1 && z <= nz - 2;
+        if (!inside) t = z == nz - 1 ? FL_LID : FL_WALL;
+    } else if (geometry == LBM_CHANNEL) {
+        if (z == 0) t = FL_WALL;
+        else if (z == nz - 1) t = FL_LID;
+    }
+    fl[i] = t;
+}
+
+// Fast-path hints: BORDER for fluid cells on a box face, NEARWALL for fluid
+// cells with a non-fluid cell among their 26 neighbours (wrapping).
+__global__ void k_flag_hints(uint8_t* fl, int nx, int ny, int nz)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = (uint64_t)nx * ny * nz;
+    if (i >= n) return;
+    if ((fl[i] & FL_TYPE) != FL_FLUID) return;
+    const int z = (int)(i % nz), y = (int)((i / nz) % ny), x = (int)(i / ((uint64_t)ny * nz));
+    uint8_t h = 0;
+    if (x == 0 || x == nx - 1 || y == 0 || y == ny - 1 || z == 0 || z == nz - 1) h |= FL_BORDER;
+    for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int xx = (x + dx + nx) % nx, yy = (y + dy + ny) % ny, zz = (z + dz + nz) % nz;
+                const uint64_t j = ((uint64_t)xx * ny + yy) * nz + zz;
+                if ((fl[j] & FL_TYPE) != FL_FLUID) h |= FL_NEARWALL;
+            }
+    fl[i] |= h;
+}
+
+__global__ void k_flag_types_only(const uint8_t* fl, uint8_t* out, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = fl[i] & FL_TYPE;
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+
+__global__ void k_count_fluid(const uint8_t* fl, uint64_t n, unsigned long long* count)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool f = i < n && (fl[i] & FL_TYPE) == FL_FLUID;
+    const unsigned long long b = __ballot(f);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+}
+
+// Sum per-block partial pairs in a fixed order (one block of 256 threads).
+__global__ void __launch_bounds__(256) k_reduce_pairs(const double* partial, int nblocks, double* result)
+{
+    __shared__ double sm[2][256];
+    double m = 0.0, e = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+        m += partial[2 * (size_t)b];
+        e += partial[2 * (size_t)b + 1];
+    }
+    sm[0][threadIdx.x] = m;
+    sm[1][threadIdx.x] = e;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sm[0][threadIdx.x] += sm[0][threadIdx.x + s];
+            sm[1][threadIdx.x] += sm[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        result[0] = sm[0][0];
+        result[1] = sm[1][0];
+    }
+}
+
+uint32_t grid_for(uint64_t n, int block) { return (uint32_t)((n + block - 1) / block); }
+
+// Streaming copy, 16 bytes per lane, grid-stride over 2048 blocks.
+__global__ void __launch_bounds__(256) k_copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+}  // namespace
+
+// --- handle --------------------------------------------------------------------
+
+struct lbm_handle {
+    lbm_desc d;
+    int q = 19;
+    int64_t ntot = 0, fluid = 0, stride = 0;
+    size_t pop_bytes = 0, out_bytes = 0, flag_bytes = 0;
+    void* pop = nullptr;
+    void* out = nullptr;
+    uint8_t* flags = nullptr;
+    bool own_pop = false, own_out = false, own_flags = false;
+    hipStream_t stream = nullptr;
+    RelaxD relax{};
+    int aa_phase = 0;
+    int64_t steps = 0;
+    int64_t first_nonfinite = -1;
+    int block = 256;
+    double* partial = nullptr;  // invariant partial sums (2 per block) + 2 results
+    int red_blocks = 0;
+    LaunchFn launch = nullptr;
+
+    Field field() const
+    {
+        Field F;
+        F.pop = pop;
+        F.out = out;
+        F.flags = flags;
+        F.stride = stride;
+        F.ntot = (uint32_t)ntot;
+        F.nx = d.nx;
+        F.ny = d.ny;
+        F.nz = d.nz;
+        return F;
+    }
+    Launch base(int op) const
+    {
+        Launch L{};
+        L.op = op;
+        L.model = d.collision;
+        L.layout = d.layout;
+        L.block = block;
+        L.grid = grid_for((uint64_t)ntot, block);
+        L.F = field();
+        L.relax = relax;
+        return L;
+    }
+};
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_error.c_str(); }
+
+void lbm_desc_default(lbm_desc* d)
+{
+    std::memset(d, 0, sizeof(*d));
+    d->lattice = 19;
+    d->nx = d->ny = d->nz = 8;
+    d->scheme = LBM_AA;
+    d->collision = LBM_BGK;
+    d->storage_dtype = LBM_F64;
+    d->layout = LBM_SOA;
+    d->geometry = LBM_CAVITY;
+    d->ptr_kind = LBM_PTR_DEVICE;
+    d->omega = 1.0;
+    d->trt_lambda = 0.25;
+    d->omega_bulk = 0.0;
+}
+
+static int validate(const lbm_desc* d)
+{
+    if (!d) return fail(LBM_EINVAL, "null description");
+    if (d->lattice != 19 && d->lattice != 27) return fail(LBM_EINVAL, "lattice must be 19 or 27");
+    const int lo = d->geometry == LBM_CAVITY ? 3 : 1;
+    if (d->nx < lo || d->ny < lo || d->nz < lo)
+        return fail(LBM_EINVAL, d->geometry == LBM_CAVITY ? "cavity dimensions must be >= 3" : "dimensions must be >= 1");
+    if (d->geometry == LBM_CHANNEL && d->nz < 3) return fail(LBM_EINVAL, "channel needs nz >= 3");
+    const int64_t n = (int64_t)d->nx * d->ny * d->nz;
+    if (n > 0x7fffffffLL) return fail(LBM_EUNSUPPORTED, "more than 2^31-1 cells");
+    if (d->scheme < LBM_2POP || d->scheme > LBM_AA) return fail(LBM_EINVAL, "unknown scheme");
+    if (d->collision < LBM_BGK || d->collision > LBM_RR) return fail(LBM_EINVAL, "unknown collision model");
+    if (d->storage_dtype < LBM_F64 || d->storage_dtype > LBM_F16_SHIFTED) return fail(LBM_EINVAL, "unknown storage dtype");
+    if (d->layout != LBM_SOA && d->layout != LBM_AOS) return fail(LBM_EINVAL, "unknown layout");
+    if (d->geometry < LBM_CAVITY || d->geometry > LBM_CHANNEL) return fail(LBM_EINVAL, "unknown geometry");
+    if (d->ptr_kind != LBM_PTR_DEVICE && d->ptr_kind != LBM_PTR_HOST) return fail(LBM_EINVAL, "unknown pointer kind");
+    if (!(d->omega > 0.0 && d->omega < 2.0)) return fail(LBM_EINVAL, "omega must lie in (0, 2)");
+    if (d->omega_bulk > 0.0 && !(d->omega_bulk < 2.0)) return fail(LBM_EINVAL, "omega_bulk must lie in (0, 2)");
+    if (d->collision == LBM_TRT && !(d->trt_lambda > 0.0)) return fail(LBM_EINVAL, "trt_lambda must be > 0");
+    const double* v = d->lid_velocity;
+    if (!(std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) < 0.4)) return fail(LBM_EINVAL, "|lid velocity| must be < 0.4");
+    if (d->block_size != 0 && d->block_size != -1 &&
+        (d->block_size < 64 || d->block_size > 1024 || d->block_size % 64 != 0))
+        return fail(LBM_EINVAL, "block_size must be a multiple of 64 in [64, 1024] (0 auto, -1 autotune)");
+    if (d->check_every < 0) return fail(LBM_EINVAL, "check_every must be >= 0");
+    return LBM_OK;
+}
+
+int lbm_required_bytes(const lbm_desc* d, size_t out[3])
+{
+    int rc = validate(d);
+    if (rc) return rc;
+    if (!out) return fail(LBM_EINVAL, "null output");
+    const int64_t n = (int64_t)d->nx * d->ny * d->nz;
+    const size_t s = elem_bytes(d->storage_dtype);
+    const size_t pop = d->layout == LBM_SOA ? (size_t)soa_stride(n) * d->lattice * s : (size_t)n * d->lattice * s;
+    out[0] = pop;
+    out[1] = d->scheme == LBM_2POP ? pop : 0;
+    out[2] = (size_t)n;
+    return LBM_OK;
+}
+
+static int run(lbm_handle* h, const Launch& L)
+{
+    hipError_t e = h->launch(L, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return LBM_OK;
+}
+
+static int init_state(lbm_handle* h, const double* rho, const double* u)
+{
+    Launch L = h->base(OP_INIT);
+    L.init.rho = rho;
+    L.init.u = u;
+    for (int a = 0; a < 3; ++a) L.init.lid[a] = h->d.lid_velocity[a];
+    int rc = run(h, L);
+    if (rc) return rc;
+    h->aa_phase = 0;
+    h->steps = 0;
+    h->first_nonfinite = -1;
+    return LBM_OK;
+}
+
+static int enqueue_steps(lbm_handle* h, int n)
+{
+    for (int s = 0; s < n; ++s) {
+        Launch L = h->base(OP_STEP);
+        if (h->d.scheme == LBM_2POP) {
+            L.kind = KIND_2POP;
+            int rc = run(h, L);
+            if (rc) return rc;
+            std::swap(h->pop, h->out);
+        } else if (h->d.scheme == LBM_SWAP) {
+            L.kind = KIND_SWAP_COLLIDE;
+            int rc = run(h, L);
+            if (rc) return rc;
+            L.kind = KIND_SWAP_STREAM;
+            rc = run(h, L);
+            if (rc) return rc;
+        } else {
+            L.kind = h->aa_phase ? KIND_AA_ODD : KIND_AA_EVEN;
+            int rc = run(h, L);
+            if (rc) return rc;
+            h->aa_phase ^= 1;
+        }
+        ++h->steps;
+    }
+    return LBM_OK;
+}
+
+static int autotune(lbm_handle* h)
+{
+    static const int cand[] = {64, 128, 256, 512, 1024};
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&b), "hipEventCreate");
+    float best = 1e30f;
+    int best_b = 256;
+    for (int c : cand) {
+        h->block = c;
+        int rc = enqueue_steps(h, 2);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(a, h->stream), "hipEventRecord");
+        rc = enqueue_steps(h, 6);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(b, h->stream), "hipEventRecord");
+        HIP_TRY(hipEventSynchronize(b), "hipEventSynchronize");
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+        if (ms < best) {
+            best = ms;
+            best_b = c;
+        }
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    h->block = best_b;
+    return LBM_OK;
+}
+
+lbm_handle* lbm_create_ex(const lbm_desc* d)
+{
+    if (validate(d)) return nullptr;
+    lbm_handle* h = new lbm_handle();
+    h->d = *d;
+    h->q = d->lattice;
+    h->ntot = (int64_t)d->nx * d->ny * d->nz;
+    h->stride = d->layout == LBM_SOA ? soa_stride(h->ntot) : h->ntot;
+    h->stream = (hipStream_t)d->stream;
+    h->launch = pick_tu(d->lattice, d->storage_dtype);
+    h->block = d->block_size > 0 ? d->block_size : 256;
+    h->relax.omega = d->omega;
+    h->relax.omega_m = d->collision == LBM_TRT ? trt_omega_minus(d->omega, d->trt_lambda) : d->omega;
+    h->relax.omega_b = d->omega_bulk > 0.0 ? d->omega_bulk : d->omega;
+    size_t req[3];
+    lbm_required_bytes(d, req);
+    h->pop_bytes = req[0];
+    h->out_bytes = req[1];
+    h->flag_bytes = req[2];
+
+    auto bail = [&](int code, const std::string& msg) -> lbm_handle* {
+        fail(code, msg);
+        if (h->own_pop && h->pop) hipFree(h->pop);
+        if (h->own_out && h->out) hipFree(h->out);
+        if (h->own_flags && h->flags) hipFree(h->flags);
+        if (h->partial) hipFree(h->partial);
+        delete h;
+        return nullptr;
+    };
+    auto alloc = [&](void** p, size_t bytes, const char* what) -> bool {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, std::string("hipMalloc ") + what + ": " + hipGetErrorString(e));
+            *p = nullptr;
+            return false;
+        }
+        return true;
+    };
+    if (d->pop) h->pop = d->pop;
+    else if (alloc(&h->pop, h->pop_bytes, "pop")) h->own_pop = true;
+    else return bail(LBM_ENOMEM, lbm_last_error());
+    if (d->scheme == LBM_2POP) {
+        if (d->out) h->out = d->out;
+        else if (alloc(&h->out, h->out_bytes, "out")) h->own_out = true;
+        else return bail(LBM_ENOMEM, lbm_last_error());
+    }
+    if (d->flags) h->flags = (uint8_t*)d->flags;
+    else if (alloc((void**)&h->flags, h->flag_bytes, "flags")) h->own_flags = true;
+    else return bail(LBM_ENOMEM, lbm_last_error());
+    for (void* p : {h->pop, h->out, (void*)h->flags})
+        if (p && ((uintptr_t)p % 256) != 0) return bail(LBM_EINVAL, "caller buffers must be 256-byte aligned");
+
+    h->red_blocks = (int)grid_for((uint64_t)h->ntot, 256);
+    if (!alloc((void**)&h->partial, sizeof(double) * (2 * (size_t)h->red_blocks + 2), "reduction"))
+        return bail(LBM_ENOMEM, lbm_last_error());
+
+    // Flags: types, then fast-path hints; count fluid cells.
+    const uint32_t g = grid_for((uint64_t)h->ntot, 256);
+    k_flag_types<<<g, 256, 0, h->stream>>>(h->flags, d->nx, d->ny, d->nz, d->geometry);
+    k_flag_hints<<<g, 256, 0, h->stream>>>(h->flags, d->nx, d->ny, d->nz);
+    unsigned long long* cnt = (unsigned long long*)h->partial;
+    k_zero_u64<<<1, 1, 0, h->stream>>>(cnt);
+    k_count_fluid<<<g, 256, 0, h->stream>>>(h->flags, (uint64_t)h->ntot, cnt);
+    unsigned long long nf = 0;
+    hipError_t e = hipMemcpyAsync(&nf, cnt, sizeof(nf), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("flag set-up: ") + hipGetErrorString(e));
+    h->fluid = (int64_t)nf;
+
+    if (init_state(h, nullptr, nullptr)) return bail(LBM_EDEVICE, lbm_last_error());
+    if (d->block_size == -1) {
+        if (autotune(h) || init_state(h, nullptr, nullptr)) return bail(LBM_EDEVICE, lbm_last_error());
+    }
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("initialisation: ") + hipGetErrorString(e));
+    return h;
+}
+
+lbm_handle* lbm_create(int lattice, int nx, int ny, int nz, int scheme, int collision, double omega, double u_lid,
+                       int storage_dtype)
+{
+    lbm_desc d;
+    lbm_desc_default(&d);
+    d.lattice = lattice;
+    d.nx = nx;
+    d.ny = ny;
+    d.nz = nz;
+    d.scheme = scheme;
+    d.collision = collision;
+    d.omega = omega;
+    d.lid_velocity[0] = u_lid;
+    d.storage_dtype = storage_dtype;
+    return lbm_create_ex(&d);
+}
+
+void lbm_destroy(lbm_handle* h)
+{
+    if (!h) return;
+    if (h->stream) hipStreamSynchronize(h->stream);
+    else hipDeviceSynchronize();
+    if (h->own_pop && h->pop) hipFree(h->pop);
+    if (h->own_out && h->out) hipFree(h->out);
+    if (h->own_flags && h->flags) hipFree(h->flags);
+    if (h->partial) hipFree(h->partial);
+    delete h;
+}
+
+// Device staging for host pointers (ptr_kind = LBM_PTR_HOST).
+struct Staging {
+    void* dev = nullptr;
+    ~Staging()
+    {
+        if (dev) hipFree(dev);
+    }
+};
+
+static int stage_in(lbm_handle* h, const void* src, size_t bytes, Staging& st, const void** dev)
+{
+    if (!src) {
+        *dev = nullptr;
+        return LBM_OK;
+    }
+    if (h->d.ptr_kind == LBM_PTR_DEVICE) {
+        *dev = src;
+        return LBM_OK;
+    }
+    HIP_TRY(hipMalloc(&st.dev, bytes), "hipMalloc staging");
+    HIP_TRY(hipMemcpyAsync(st.dev, src, bytes, hipMemcpyHostToDevice, h->stream), "hipMemcpyAsync");
+    *dev = st.dev;
+    return LBM_OK;
+}
+
+static int stage_out_alloc(lbm_handle* h, void* dst, size_t bytes, Staging& st, void** dev)
+{
+    if (h->d.ptr_kind == LBM_PTR_DEVICE) {
+        *dev = dst;
+        return LBM_OK;
+    }
+    HIP_TRY(hipMalloc(&st.dev, bytes), "hipMalloc staging");
+    *dev = st.dev;
+    return LBM_OK;
+}
+
+static int stage_out_finish(lbm_handle* h, void* dst, size_t bytes, Staging& st)
+{
+    if (h->d.ptr_kind == LBM_PTR_HOST)
+        HIP_TRY(hipMemcpyAsync(dst, st.dev, bytes, hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return LBM_OK;
+}
+
+int lbm_init_equilibrium(lbm_handle* h, const double* rho, const double* u)
+{
+    if (!h) return fail(LBM_EINVAL, "null handle");
+    Staging sr, su;
+    const void *dr, *du;
+    int rc = stage_in(h, rho, sizeof(double) * h->ntot, sr, &dr);
+    if (!rc) rc = stage_in(h, u, sizeof(double) * 3 * h->ntot, su, &du);
+    if (!rc) rc = init_state(h, (const double*)dr, (const double*)du);
+    if (!rc && h->d.ptr_kind == LBM_PTR_HOST) HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return rc;
+}
+
+static int invariants_raw(lbm_handle* h, double* mass, double* ke)
+{
+    Launch L = h->base(OP_INVARIANTS);
+    L.block = 256;
+    L.grid = (uint32_t)h->red_blocks;
+    L.aa_odd = h->d.scheme == LBM_AA ? h->aa_phase : 0;
+    L.d0 = h->partial;
+    int rc = run(h, L);
+    if (rc) return rc;
+    double* res = h->partial + 2 * (size_t)h->red_blocks;
+    k_reduce_pairs<<<1, 256, 0, h->stream>>>(h->partial, h->red_blocks, res);
+    double hr[2];
+    HIP_TRY(hipMemcpyAsync(hr, res, sizeof(hr), hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    *mass = hr[0];
+    *ke = hr[1];
+    return LBM_OK;
+}
+
+int lbm_step(lbm_handle* h, int n)
+{
+    if (!h) return fail(LBM_EINVAL, "null handle");
+    if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+    const int K = h->d.check_every;
+    while (n > 0) {
+        int chunk = n;
+        if (K > 0) chunk = std::min<int64_t>(n, K - (h->steps % K));
+        int rc = enqueue_steps(h, chunk);
+        if (rc) return rc;
+        n -= chunk;
+        if (K > 0 && h->steps % K == 0) {
+            double m, e;
+            rc = invariants_raw(h, &m, &e);
+            if (rc) return rc;
+            if (!std::isfinite(m) || !std::isfinite(e)) {
+                if (h->first_nonfinite < 0) h->first_nonfinite = h->steps;
+                return fail(LBM_ENONFINITE, "non-finite mass or kinetic energy at step " + std::to_string(h->steps));
+            }
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_macroscopic(lbm_handle* h, double* rho, double* u)
+{
+    if (!h || !rho || !u) return fail(LBM_EINVAL, "null argument");
+    Staging sr, su;
+    void *dr, *du;
+    int rc = stage_out_alloc(h, rho, sizeof(double) * h->ntot, sr, &dr);
+    if (!rc) rc = stage_out_alloc(h, u, sizeof(double) * 3 * h->ntot, su, &du);
+    if (rc) return rc;
+    Launch L = h->base(OP_MACRO);
+    L.aa_odd = h->d.scheme == LBM_AA ? h->aa_phase : 0;
+    L.d0 = (double*)dr;
+    L.d1 = (double*)du;
+    rc = run(h, L);
+    if (!rc) rc = stage_out_finish(h, rho, sizeof(double) * h->ntot, sr);
+    if (!rc) rc = stage_out_finish(h, u, sizeof(double) * 3 * h->ntot, su);
+    return rc;
+}
+
+int lbm_get_populations(lbm_handle* h, double* f)
+{
+    if (!h || !f) return fail(LBM_EINVAL, "null argument");
+    Staging s;
+    void* df;
+    const size_t bytes = sizeof(double) * h->q * h->ntot;
+    int rc = stage_out_alloc(h, f, bytes, s, &df);
+    if (rc) return rc;
+    Launch L = h->base(OP_GET);
+    L.aa_odd = h->d.scheme == LBM_AA ? h->aa_phase : 0;
+    L.d0 = (double*)df;
+    rc = run(h, L);
+    if (!rc) rc = stage_out_finish(h, f, bytes, s);
+    return rc;
+}
+
+int lbm_get_populations_at(lbm_handle* h, const int64_t* cells, int n, double* f)
+{
+    if (!h || !cells || !f || n < 0) return fail(LBM_EINVAL, "bad argument");
+    if (n == 0) return LBM_OK;
+    if (h->d.ptr_kind == LBM_PTR_HOST)
+        for (int j = 0; j < n; ++j)
+            if (cells[j] < 0 || cells[j] >= h->ntot) return fail(LBM_EINVAL, "cell index out of range");
+    Staging si, so;
+    const void* dc;
+    void* df;
+    int rc = stage_in(h, cells, sizeof(int64_t) * n, si, &dc);
+    if (!rc) rc = stage_out_alloc(h, f, sizeof(double) * n * h->q, so, &df);
+    if (rc) return rc;
+    Launch L = h->base(OP_GET_CELLS);
+    L.aa_odd = h->d.scheme == LBM_AA ? h->aa_phase : 0;
+    L.cells = (const int64_t*)dc;
+    L.d0 = (double*)df;
+    L.n = n;
+    L.grid = grid_for((uint64_t)n, L.block);
+    rc = run(h, L);
+    if (!rc) rc = stage_out_finish(h, f, sizeof(double) * n * h->q, so);
+    return rc;
+}
+
+int lbm_set_populations(lbm_handle* h, const double* f)
+{
+    if (!h || !f) return fail(LBM_EINVAL, "null argument");
+    Staging s;
+    const void* df;
+    int rc = stage_in(h, f, sizeof(double) * h->q * h->ntot, s, &df);
+    if (rc) return rc;
+    Launch L = h->base(OP_SET);
+    L.c0 = (const double*)df;
+    rc = run(h, L);
+    if (rc) return rc;
+    h->aa_phase = 0;
+    h->steps = 0;
+    h->first_nonfinite = -1;
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return LBM_OK;
+}
+
+int lbm_get_flags(lbm_handle* h, uint8_t* flags)
+{
+    if (!h || !flags) return fail(LBM_EINVAL, "null argument");
+    Staging s;
+    void* df;
+    int rc = stage_out_alloc(h, flags, (size_t)h->ntot, s, &df);
+    if (rc) return rc;
+    k_flag_types_only<<<grid_for((uint64_t)h->ntot, 256), 256, 0, h->stream>>>(h->flags, (uint8_t*)df, (uint64_t)h->ntot);
+    HIP_TRY(hipGetLastError(), "kernel launch");
+    return stage_out_finish(h, flags, (size_t)h->ntot, s);
+}
+
+int lbm_invariants(lbm_handle* h, double* mass, double* kinetic_energy)
+{
+    if (!h || !mass || !kinetic_energy) return fail(LBM_EINVAL, "null argument");
+    return invariants_raw(h, mass, kinetic_energy);
+}
+
+int lbm_neighbor_index(lbm_handle* h, const int64_t* cells, int n, int64_t* out)
+{
+    if (!h || !cells || !out || n < 0) return fail(LBM_EINVAL, "bad argument");
+    if (n == 0) return LBM_OK;
+    Staging si, so;
+    const void* dc;
+    void* dout;
+    int rc = stage_in(h, cells, sizeof(int64_t) * n, si, &dc);
+    if (!rc) rc = stage_out_alloc(h, out, sizeof(int64_t) * n * h->q, so, &dout);
+    if (rc) return rc;
+    if (h->d.ptr_kind == LBM_PTR_HOST) {
+        for (int j = 0; j < n; ++j)
+            if (cells[j] < 0 || cells[j] >= h->ntot) return fail(LBM_EINVAL, "cell index out of range");
+    }
+    Launch L = h->base(OP_NEIGHBORS);
+    L.cells = (const int64_t*)dc;
+    L.idx_out = (int64_t*)dout;
+    L.n = n;
+    L.grid = grid_for((uint64_t)n, L.block);
+    rc = run(h, L);
+    if (!rc) rc = stage_out_finish(h, out, sizeof(int64_t) * n * h->q, so);
+    return rc;
+}
+
+int lbm_get_info(lbm_handle* h, lbm_info* info)
+{
+    if (!h || !info) return fail(LBM_EINVAL, "null argument");
+    info->ntot = h->ntot;
+    info->fluid_cells = h->fluid;
+    info->pop_stride = h->stride;
+    info->steps_done = h->steps;
+    info->first_nonfinite = h->first_nonfinite;
+    const int64_t s = (int64_t)elem_bytes(h->d.storage_dtype);
+    info->bytes_per_update = h->d.scheme == LBM_SWAP ? 4 * h->q * s + 2 : 2 * h->q * s + 1;
+    info->aa_phase = h->aa_phase;
+    info->block_size = h->block;
+    return LBM_OK;
+}
+
+int lbm_lattice(int lattice, int32_t* c, double* t, int32_t* opp)
+{
+    if (lattice != 19 && lattice != 27) return fail(LBM_EINVAL, "lattice must be 19 or 27");
+    if (!c || !t || !opp) return fail(LBM_EINVAL, "null argument");
+    auto fill = [&](auto s) {
+        for (int k = 0; k < lattice; ++k) {
+            for (int a = 0; a < 3; ++a) c[3 * k + a] = s.c[k][a];
+            t[k] = s.t[k];
+            opp[k] = s.opp[k];
+        }
+    };
+    if (lattice == 19) fill(make_stencil<19>());
+    else fill(make_stencil<27>());
+    return LBM_OK;
+}
+
+int lbm_device_copy(void* dst, const void* src, size_t bytes, void* stream)
+{
+    if (!dst || !src || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16)
+        return fail(LBM_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+    if (bytes == 0) return LBM_OK;
+    const uint64_t n = bytes / 16;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_for(n, 256), 8192);
+    k_copy16<<<grid, 256, 0, (hipStream_t)stream>>>((uint4*)dst, (const uint4*)src, n);
+    HIP_TRY(hipGetLastError(), "copy launch");
+    return LBM_OK;
+}
+
+int lbm_sync(lbm_handle* h)
+{
+    if (!h) return fail(LBM_EINVAL, "null handle");
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return LBM_OK;
+}
+
+}  // extern "C"

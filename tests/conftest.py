@@ -26,3 +26,14 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session")
+def hiplib():
+    """The built HIP library (built first if nothing is built)."""
+    from paper_2010_11751_amd import build as hip_build
+    if not os.path.exists(hip_build.LIB):
+        hip_build.build()
+    from paper_2010_11751_amd import lbm
+    lbm.lib()
+    return lbm

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every symbol include/lbm.h declares, its lattice tables equal the
+oracle's element by element, and argument validation rejects bad input
+before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for must in ("lbm_create", "lbm_step", "lbm_macroscopic", "lbm_batch_step", "lbm_batch_create",
+                 "lbm_get_populations", "lbm_set_populations", "lbm_invariants", "lbm_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(hiplib):
+    L = hiplib.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(hiplib.SYMBOLS) == declared_functions()
+
+
+@pytest.mark.parametrize("q", (19, 27))
+def test_kernel_tables_equal_oracle_tables(hiplib, orc, q):
+    c, t, opp = hiplib.lattice(q)
+    oc, ot, oopp = orc.lattice(q)
+    assert np.array_equal(c, oc)
+    assert np.array_equal(opp, oopp)
+    assert np.abs(t - ot).max() <= 1e-17
+
+
+def _desc(hiplib, **kw):
+    d = hiplib.Desc()
+    hiplib.lib().lbm_desc_default(ctypes.byref(d))
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("lattice", 20, "lattice"), ("nx", 2, "dimensions"), ("omega", 2.0, "omega"), ("omega", 0.0, "omega"),
+    ("scheme", 7, "scheme"), ("collision", 9, "collision"), ("storage_dtype", 5, "dtype"),
+    ("layout", 3, "layout"), ("block_size", 96, "block_size"), ("check_every", -1, "check_every"),
+])
+def test_invalid_descriptions_are_rejected(hiplib, field, value, needle):
+    d = _desc(hiplib, **{field: value})
+    out = (ctypes.c_size_t * 3)()
+    assert hiplib.lib().lbm_required_bytes(ctypes.byref(d), out) == hiplib.EINVAL
+    assert needle in hiplib.last_error()
+    assert not hiplib.lib().lbm_create_ex(ctypes.byref(d))
+
+
+def test_fast_lid_is_rejected(hiplib):
+    assert not hiplib.lib().lbm_create(19, 8, 8, 8, 2, 0, 1.0, 0.5, 0)
+    assert "lid" in hiplib.last_error()
+
+
+@pytest.mark.parametrize("scheme,dtype,layout", [(0, 0, 0), (2, 1, 0), (1, 2, 1)])
+def test_required_bytes(hiplib, scheme, dtype, layout):
+    d = _desc(hiplib, nx=10, ny=11, nz=12, scheme=scheme, storage_dtype=dtype, layout=layout)
+    out = (ctypes.c_size_t * 3)()
+    assert hiplib.lib().lbm_required_bytes(ctypes.byref(d), out) == 0
+    n = 10 * 11 * 12
+    s = (8, 4, 2)[dtype]
+    stride = (n + 1023) // 1024 * 1024 if layout == 0 else n
+    assert out[0] == 19 * stride * s
+    assert out[1] == (out[0] if scheme == 0 else 0)
+    assert out[2] == n
+
+
+def test_null_handles_are_rejected(hiplib):
+    L = hiplib.lib()
+    assert L.lbm_step(None, 1) == hiplib.EINVAL
+    assert L.lbm_sync(None) == hiplib.EINVAL
+    assert L.lbm_batch_step(None, 1) == hiplib.EINVAL
+    assert not L.lbm_batch_create(0, None, 2, 0, 0, None)
+    L.lbm_destroy(None)
+    L.lbm_batch_destroy(None)

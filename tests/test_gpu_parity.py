@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path against the FP64 CPU oracle, through the C ABI.
+
+FP64 storage must match the oracle to max |df| <= 1e-12 (populations are of
+order 0.05-0.4, so this is a few hundred ulps of headroom for the different
+but algebraically equal operation order). Flags and neighbour indices are
+compared bit for bit. Small cases span several 256-thread blocks and a
+ragged tail; every scheme x collision x layout x lattice is covered.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2010_11751_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+SCHEMES = ("2pop", "swap", "aa")
+COLLS = ("bgk", "trt", "reg", "rr")
+GEOM = {"cavity": O.CAVITY, "periodic": O.PERIODIC, "channel": O.CHANNEL}
+
+
+@pytest.fixture(scope="module")
+def lbm(hiplib):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return hiplib
+
+
+def oracle_cfg(q, nx, ny, nz, coll, omega, u_lid=(0.0, 0.0, 0.0), geometry="cavity", omega_bulk=None, lam=0.25):
+    return O.Config(q=q, nx=nx, ny=ny, nz=nz, geometry=GEOM[geometry], model=O.MODELS[coll], omega=omega,
+                    trt_lambda=lam, omega_bulk=omega_bulk, u_lid=tuple(u_lid))
+
+
+def max_err(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max())
+
+
+def test_config_small_cavity_matches_oracle(lbm):
+    """D3Q19 BGK 32^3 cavity, FP64 2Pop SoA, lid 0.02, Re 100, 100 steps."""
+    cav = W.CAVITY_SMALL
+    print(f"case: 32^3 BGK 2pop f64 omega={cav.omega:.6f}", flush=True)
+    sim = lbm.Lattice(19, cav.n, scheme="2pop", collision="bgk", omega=cav.omega, u_lid=cav.u_lid)
+    cfg = oracle_cfg(19, cav.n, cav.n, cav.n, "bgk", cav.omega, (cav.u_lid, 0, 0))
+    ref = O.Simulation(cfg, "2pop")
+    assert np.array_equal(sim.flags().cpu().numpy(), ref.flags)
+    sim.step(100)
+    ref.step(100)
+    assert max_err(sim.populations().cpu().numpy(), ref.populations()) <= TOL
+    rho, u = sim.macroscopic()
+    rr, ur = ref.macroscopic()
+    assert max_err(rho.cpu().numpy(), rr) <= TOL
+    assert max_err(u.cpu().numpy(), ur) <= TOL
+    info = sim.info()
+    assert info.fluid_cells == 30 ** 3 and info.steps_done == 100
+
+
+@pytest.mark.parametrize("q", (19, 27))
+@pytest.mark.parametrize("layout", ("soa", "aos"))
+@pytest.mark.parametrize("coll", COLLS)
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_scheme_collision_layout_sweep(lbm, q, layout, coll, scheme):
+    nx, ny, nz, omega = 12, 10, 14, 1.71
+    ob = 1.3 if coll in ("reg", "rr") else None
+    print(f"case: q={q} {scheme} {coll} {layout} {nx}x{ny}x{nz}", flush=True)
+    sim = lbm.Lattice(q, nx, ny, nz, scheme=scheme, collision=coll, omega=omega, u_lid=0.05, layout=layout,
+                      omega_bulk=ob)
+    ref = O.Simulation(oracle_cfg(q, nx, ny, nz, coll, omega, (0.05, 0, 0), omega_bulk=ob), "ref")
+    for n in (21, 1):   # odd, then even step count (AA phase read-out both ways)
+        sim.step(n)
+        ref.step(n)
+        assert max_err(sim.populations().cpu().numpy(), ref.populations()) <= TOL, n
+
+
+@pytest.mark.parametrize("q", (19, 27))
+@pytest.mark.parametrize("geometry", ("periodic", "channel"))
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_wrapping_geometries_from_a_velocity_field(lbm, q, geometry, scheme):
+    nx, ny, nz = 9, 8, 11
+    u0 = W.random_velocity(61, nx * ny * nz, amp=0.04).T.copy()
+    rho0 = W.random_density(62, nx * ny * nz, 0.98, 1.02)
+    print(f"case: q={q} {geometry} {scheme}", flush=True)
+    sim = lbm.Lattice(q, nx, ny, nz, scheme=scheme, collision="trt", omega=1.4, geometry=geometry,
+                      lid_velocity=(0.03, -0.01, 0.0))
+    sim.init_equilibrium(torch.from_numpy(rho0), torch.from_numpy(u0))
+    cfg = oracle_cfg(q, nx, ny, nz, "trt", 1.4, (0.03, -0.01, 0.0), geometry=geometry)
+    ref = O.Simulation(cfg, "ref", rho=rho0, u=u0)
+    assert max_err(sim.populations().cpu().numpy(), ref.populations()) <= 1e-15
+    sim.step(13)
+    ref.step(13)
+    assert max_err(sim.populations().cpu().numpy(), ref.populations()) <= TOL
+
+
+@pytest.mark.parametrize("q", (19, 27))
+def test_rr_equilibrium_initialisation(lbm, q):
+    n = 7
+    u0 = W.random_velocity(63, n ** 3, amp=0.05).T.copy()
+    sim = lbm.Lattice(q, n, scheme="aa", collision="rr", omega=1.9, geometry="periodic")
+    sim.init_equilibrium(None, torch.from_numpy(u0))
+    ref = O.Simulation(oracle_cfg(q, n, n, n, "rr", 1.9, geometry="periodic"), "ref", u=u0)
+    assert max_err(sim.populations().cpu().numpy(), ref.populations()) <= 1e-15
+
+
+def test_flags_and_neighbour_indices_bit_exact(lbm):
+    for geometry, dims in (("cavity", (9, 7, 11)), ("periodic", (5, 6, 7)), ("channel", (6, 5, 8))):
+        for q in (19, 27):
+            sim = lbm.Lattice(q, *dims, geometry=geometry)
+            cfg = oracle_cfg(q, *dims, "bgk", 1.0, geometry=geometry)
+            assert np.array_equal(sim.flags().cpu().numpy(), O.flags(cfg))
+            n = dims[0] * dims[1] * dims[2]
+            cells = np.arange(n)
+            fl = O.flags(cfg)
+            got = sim.neighbor_index(cells).cpu().numpy()
+            for i in cells:
+                if fl[i] != O.FLUID and geometry == "cavity":
+                    continue   # wall cells never stream; their neighbours may lie outside the box
+                for k in range(q):
+                    assert got[i, k] == O.neighbour_index(cfg, int(i), k), (geometry, q, i, k)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("dtype", ("f64", "f32"))
+def test_checkpoint_round_trip_is_bit_exact(lbm, scheme, dtype):
+    """51 steps, save, destroy, create, restore, 49 steps == 100 steps."""
+    kw = dict(scheme=scheme, collision="trt", omega=1.8, u_lid=0.04, dtype=dtype)
+    a = lbm.Lattice(19, 13, 11, 12, **kw)
+    a.step(100)
+    want = a.populations().cpu()
+    b = lbm.Lattice(19, 13, 11, 12, **kw)
+    b.step(51)
+    saved = b.populations().cpu()
+    b.close()
+    c = lbm.Lattice(19, 13, 11, 12, **kw)
+    c.set_populations(saved)
+    c.step(49)
+    assert torch.equal(c.populations().cpu(), want)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_invariants_match_oracle(lbm, scheme):
+    sim = lbm.Lattice(19, 16, 14, 15, scheme=scheme, collision="bgk", omega=1.6, u_lid=0.06)
+    ref = O.Simulation(oracle_cfg(19, 16, 14, 15, "bgk", 1.6, (0.06, 0, 0)), "ref")
+    m0, _ = sim.invariants()
+    sim.step(31)
+    ref.step(31)
+    m, e = sim.invariants()
+    rm, re_ = ref.invariants()
+    assert abs(m - rm) <= 1e-12 * rm
+    assert abs(e - re_) <= 1e-10 * re_
+    assert abs(m - m0) <= 1e-12 * m0    # closed cavity conserves mass
+
+
+def test_monitor_reports_non_finite_step(lbm):
+    """A NaN planted from the host is caught by the invariant monitor at the
+    first check after it appears; the kernels themselves run normally."""
+    sim = lbm.Lattice(19, 10, scheme="aa", collision="bgk", omega=1.2, check_every=4)
+    sim.step(4)
+    f = sim.populations().cpu()
+    f[3, 5 * 100 + 5 * 10 + 5] = float("nan")
+    sim.set_populations(f)
+    sim.step(3)
+    with pytest.raises(lbm.LBMError) as e:
+        sim.step(2)
+    assert e.value.code == lbm.ENONFINITE
+    assert sim.info().first_nonfinite == 4
+
+
+def test_host_pointer_path_and_library_buffers(lbm):
+    """lbm_create_ex with library-owned buffers, the null stream and host pointers."""
+    import ctypes
+    L = lbm.lib()
+    d = lbm.Desc()
+    L.lbm_desc_default(ctypes.byref(d))
+    d.nx, d.ny, d.nz, d.scheme, d.collision, d.omega = 10, 9, 11, 0, 1, 1.5
+    d.lid_velocity[0] = 0.05
+    d.ptr_kind = 1
+    h = L.lbm_create_ex(ctypes.byref(d))
+    assert h, lbm.last_error()
+    try:
+        assert L.lbm_step(h, 9) == 0
+        f = np.zeros((19, 990))
+        assert L.lbm_get_populations(h, f.ctypes.data) == 0
+        ref = O.Simulation(oracle_cfg(19, 10, 9, 11, "trt", 1.5, (0.05, 0, 0)), "ref")
+        ref.step(9)
+        assert max_err(f, ref.populations()) <= TOL
+        rho, u = np.zeros(990), np.zeros((3, 990))
+        assert L.lbm_macroscopic(h, rho.ctypes.data, u.ctypes.data) == 0
+        rr, ur = ref.macroscopic()
+        assert max_err(rho, rr) <= TOL and max_err(u, ur) <= TOL
+        cells = np.array([0, 5, 989, 990], np.int64)
+        out = np.zeros((4, 19), np.int64)
+        assert L.lbm_neighbor_index(h, cells.ctypes.data, 4, out.ctypes.data) == lbm.EINVAL
+    finally:
+        L.lbm_destroy(h)
+
+
+def relative_l2(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+
+
+@pytest.mark.parametrize("dtype,bound", [("f32", 1e-5), ("f16", 1e-3)])
+def test_shifted_storage_taylor_green(lbm, dtype, bound):
+    """Shifted storage g = f - t_k with FP32 arithmetic vs the FP64 oracle:
+    velocity relative L2 on a periodic Taylor-Green vortex (u0 = 0.04)."""
+    n, steps, omega = 32, 200, W.omega_from_nu(0.01)
+    u0 = W.taylor_green_velocity(n, n, n, W.TGV_U0)
+    sim = lbm.Lattice(19, n, scheme="aa", collision="bgk", omega=omega, geometry="periodic", dtype=dtype)
+    sim.init_equilibrium(None, torch.from_numpy(u0))
+    ref = O.Simulation(oracle_cfg(19, n, n, n, "bgk", omega, geometry="periodic"), "2pop", u=u0)
+    sim.step(steps)
+    ref.step(steps)
+    _, u = sim.macroscopic()
+    _, ur = ref.macroscopic()
+    err = relative_l2(u.cpu().numpy(), ur)
+    print(f"{dtype}: velocity rel L2 = {err:.3e}", flush=True)
+    assert err <= bound
+
+
+@pytest.mark.parametrize("dtype,bound", [("f32", 1e-5), ("f16", 1e-3)])
+def test_shifted_storage_cavity(lbm, dtype, bound):
+    cav = W.CAVITY_SMALL
+    sim = lbm.Lattice(19, cav.n, scheme="aa", collision="bgk", omega=cav.omega, u_lid=cav.u_lid, dtype=dtype)
+    ref = O.Simulation(oracle_cfg(19, cav.n, cav.n, cav.n, "bgk", cav.omega, (cav.u_lid, 0, 0)), "2pop")
+    sim.step(100)
+    ref.step(100)
+    _, u = sim.macroscopic()
+    _, ur = ref.macroscopic()
+    err = relative_l2(u.cpu().numpy(), ur)
+    print(f"{dtype}: cavity velocity rel L2 = {err:.3e}", flush=True)
+    assert err <= bound
