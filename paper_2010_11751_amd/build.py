@@ -28,6 +28,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
+    # Fused multiply-adds only where one source expression has a*b + c, so
+    # every kernel that inlines the collision computes it bit-identically.
+    "-ffp-contract=on",
     # Packed FP32 instructions stay off (hipcc would otherwise form them from
     # float code).
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

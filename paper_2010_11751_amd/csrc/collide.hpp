@@ -26,7 +26,7 @@ template <int Q, class R>
 struct CellMoments {
     R s[L<Q>::half];  // g_k + g_kbar for k < half
     R d[L<Q>::half];  // g_k - g_kbar for k < half
-    R base, rho, u[3];
+    R base, rho, j[3], u[3];
 };
 
 template <int Q, bool SHIFT, class R>
@@ -52,14 +52,17 @@ __device__ __forceinline__ void cell_moments(const R (&g)[Q], CellMoments<Q, R>&
     m.base = rs;
     m.rho = SHIFT ? R(1) + rs : rs;
     const R inv = R(1) / m.rho;
-    m.u[0] = j[0] * inv;
-    m.u[1] = j[1] * inv;
-    m.u[2] = j[2] * inv;
+    static_for<0, 3>([&](auto D) {
+        m.j[D] = j[D];
+        m.u[D] = j[D] * inv;
+    });
 }
 
 // Second-order weighted equilibrium (BGK-W2, Sec. 2.6) split into the part
 // even in c_k and the part odd in c_k: E_k = sym_k + anti_k, E_kbar = sym_k -
-// anti_k, which is Eq. symmetry_Ek with anti_k = 3 rho t_k c_k.u.
+// anti_k, which is Eq. symmetry_Ek with anti_k = 3 t_k c_k.(rho u). The odd
+// part is formed from the momentum j = rho u itself, so that the rounding of
+// rho = 1 + base in FP32 never enters the linear term.
 template <int Q, class R>
 struct Eq2 {
     R sym[L<Q>::half];
@@ -68,27 +71,32 @@ struct Eq2 {
 };
 
 template <int Q, class R>
-__device__ __forceinline__ void equilibrium2(R base, R rho, const R (&u)[3], Eq2<Q, R>& e)
+__device__ __forceinline__ void equilibrium2(R base, R rho, const R (&j)[3], const R (&u)[3], Eq2<Q, R>& e)
 {
     using S = L<Q>;
     const R usq15 = R(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     e.rest = R(S::t(S::rest)) * (base - rho * usq15);
     static_for<0, S::half>([&](auto K) {
         constexpr int k = K;
-        R cu = R(0);
+        R cu = R(0), cj = R(0);
         static_for<0, 3>([&](auto D) {
             constexpr int a = D;
-            if constexpr (S::c(k, a) == 1) cu += u[a];
-            else if constexpr (S::c(k, a) == -1) cu -= u[a];
+            if constexpr (S::c(k, a) == 1) {
+                cu += u[a];
+                cj += j[a];
+            } else if constexpr (S::c(k, a) == -1) {
+                cu -= u[a];
+                cj -= j[a];
+            }
         });
         const R tk = R(S::t(k));
         e.sym[k] = tk * (base + rho * (R(4.5) * cu * cu - usq15));
-        e.anti[k] = (tk * R(3)) * rho * cu;
+        e.anti[k] = (tk * R(3)) * cj;
     });
 }
 
 // Hermite coefficient A_n of the regularized models for the compile-time
-// multi-index J of the support set: A_0 = base, A_a = rho u_a, and for
+// multi-index J of the support set: A_0 = base, A_a = j_a (= rho u_a), and for
 // |n| >= 2, A_n = rho u^n + a1_n where a1_n is the relaxed non-equilibrium
 // coefficient: Pi*_ab at order two and, beyond, the pair-sum recursion
 // a1_{a1..am} = sum_{l<j} (prod_{r != l,j} u_{ar}) Pi*_{al aj}.
@@ -107,18 +115,18 @@ constexpr IndexList index_list(MultiIndex m)
 }
 
 template <int Q, bool REC, int J, class R>
-__device__ __forceinline__ R hermite_coefficient(R base, R rho, const R (&u)[3], const R (&P)[3][3])
+__device__ __forceinline__ R hermite_coefficient(R base, R rho, const R (&j)[3], const R (&u)[3], const R (&P)[3][3])
 {
     constexpr MultiIndex mi = HS<Q, REC>::m(J);
     constexpr IndexList il = index_list(mi);
     if constexpr (il.len == 0) {
         return base;
+    } else if constexpr (il.len == 1) {
+        return j[il.idx[0]];
     } else {
-        R un = rho;
-        static_for<0, il.len>([&](auto Rr) { un *= u[il.idx[Rr]]; });
-        if constexpr (il.len == 1) {
-            return un;
-        } else {
+        R un = j[il.idx[0]];
+        static_for<1, il.len>([&](auto Rr) { un *= u[il.idx[Rr]]; });
+        {
             R a1 = R(0);
             static_for<0, il.len>([&](auto Lc) {
                 constexpr int l = Lc;
@@ -166,6 +174,39 @@ __device__ __forceinline__ void from_hermite(const R (&A)[HS<Q, REC>::size], R (
     });
 }
 
+// Exact conservation of mass and momentum in FP32 arithmetic. Every model
+// conserves rho and j exactly in real numbers, but with weights rounded to
+// FP32 (3 t_k is 1/6 and 1/12 only up to a relative 3e-8) the collision
+// scales j by the same 1 + O(1e-8) factor in every cell at every step, a drift
+// that accumulates linearly. Returning the (tiny) mass and momentum residuals
+// to the rest population and to the three axis pairs removes it; in exact
+// arithmetic this changes nothing.
+template <int Q, class R>
+__device__ __forceinline__ void conserve(R (&g)[Q], R base, const R (&j)[3])
+{
+    using S = L<Q>;
+    static_assert(S::c(0, 0) == -1 && S::c(1, 1) == -1 && S::c(2, 2) == -1, "k = 0, 1, 2 are -e_x, -e_y, -e_z");
+    R mo = g[S::rest];
+    R jo[3] = {R(0), R(0), R(0)};
+    static_for<0, S::half>([&](auto K) {
+        constexpr int k = K;
+        mo += g[k] + g[S::opp(k)];
+        const R dk = g[k] - g[S::opp(k)];
+        static_for<0, 3>([&](auto D) {
+            constexpr int a = D;
+            if constexpr (S::c(k, a) == 1) jo[a] += dk;
+            else if constexpr (S::c(k, a) == -1) jo[a] -= dk;
+        });
+    });
+    g[S::rest] += base - mo;
+    static_for<0, 3>([&](auto D) {
+        constexpr int a = D;
+        const R d = R(0.5) * (j[a] - jo[a]);
+        g[S::opp(a)] += d;
+        g[a] -= d;
+    });
+}
+
 template <int Q, int MODEL, bool SHIFT, class R>
 __device__ __forceinline__ void collide(R (&g)[Q], const Relax<R>& p)
 {
@@ -175,7 +216,7 @@ __device__ __forceinline__ void collide(R (&g)[Q], const Relax<R>& p)
 
     if constexpr (MODEL == BGK || MODEL == TRT) {
         Eq2<Q, R> e;
-        equilibrium2<Q>(m.base, m.rho, m.u, e);
+        equilibrium2<Q>(m.base, m.rho, m.j, m.u, e);
         const R w = p.omega;
         g[S::rest] = g[S::rest] + w * (e.rest - g[S::rest]);
         if constexpr (MODEL == BGK) {
@@ -211,7 +252,7 @@ __device__ __forceinline__ void collide(R (&g)[Q], const Relax<R>& p)
                     if constexpr (cc == 1) acc += m.s[k];
                     else if constexpr (cc == -1) acc -= m.s[k];
                 });
-                acc -= m.rho * m.u[a] * m.u[b];
+                acc -= m.j[a] * m.u[b];
                 if constexpr (a == b) acc -= m.base * R(1.0 / 3.0);
                 P[a][b] = acc;
             });
@@ -232,10 +273,11 @@ __device__ __forceinline__ void collide(R (&g)[Q], const Relax<R>& p)
         R A[H::size];
         static_for<0, H::size>([&](auto Jc) {
             constexpr int j = Jc;
-            A[j] = hermite_coefficient<Q, REC, j>(m.base, m.rho, m.u, P);
+            A[j] = hermite_coefficient<Q, REC, j>(m.base, m.rho, m.j, m.u, P);
         });
         from_hermite<Q, REC>(A, g);
     }
+    if constexpr (SHIFT) conserve<Q>(g, m.base, m.j);
 }
 
 // Equilibrium of the model at (rho, u) in the storage representation
@@ -245,18 +287,19 @@ __device__ __forceinline__ void equilibrium(R rho, const R (&u)[3], R (&g)[Q])
 {
     using S = L<Q>;
     const R base = SHIFT ? rho - R(1) : rho;
+    const R j[3] = {rho * u[0], rho * u[1], rho * u[2]};
     if constexpr (MODEL == RR) {
         using H = HS<Q, true>;
         R P[3][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
         R A[H::size];
         static_for<0, H::size>([&](auto Jc) {
-            constexpr int j = Jc;
-            A[j] = hermite_coefficient<Q, true, j>(base, rho, u, P);
+            constexpr int jj = Jc;
+            A[jj] = hermite_coefficient<Q, true, jj>(base, rho, j, u, P);
         });
         from_hermite<Q, true>(A, g);
     } else {
         Eq2<Q, R> e;
-        equilibrium2<Q>(base, rho, u, e);
+        equilibrium2<Q>(base, rho, j, u, e);
         g[S::rest] = e.rest;
         static_for<0, S::half>([&](auto K) {
             constexpr int k = K;
