@@ -111,6 +111,27 @@ def run_case(scheme, coll, dtype, steps, warmup, cav):
     }
 
 
+def traffic_run(cav):
+    import torch
+    from paper_2010_11751_amd import lbm
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    lbm.device_copy(b, a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+    for dtype in ("f64", "f32"):
+        sim = lbm.Lattice(19, cav.n, scheme="aa", collision="bgk", omega=cav.omega, u_lid=cav.u_lid, dtype=dtype)
+        sim.step(4)
+        sim.sync()
+        info = sim.info()
+        print(json.dumps({"traffic_run": dtype, "fluid_cells": info.fluid_cells,
+                          "algorithmic_bytes_per_launch": info.fluid_cells * info.bytes_per_update,
+                          "copy_bytes": 2 * nbytes}), flush=True)
+        sim.close()
+
+
 def cpu_baseline(cav, budget_s: float = 12.0, max_steps: int = 20):
     """The FP64 oracle (2Pop, BGK) on the host cores, on the same 256^3
     cavity, timed over as many whole steps as fit in about budget_s."""
@@ -138,6 +159,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-sweep", action="store_true", help="skip the nine FP64 scheme x collision runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--traffic", action="store_true",
+                    help="short run for hardware byte counters: one 1 GiB device copy, then 4 AA BGK steps of "
+                         "the 256^3 cavity in FP64 and in FP32-shifted storage")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the cavity step runs on a single MI355X; "
@@ -151,6 +175,9 @@ def main():
         sys.exit(1)
     cav = W.CAVITY_256
     print(f"# device: {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
+    if args.traffic:
+        traffic_run(cav)
+        return
 
     head = run_case("aa", "bgk", "f64", args.steps, args.warmup, cav)
     print(f"# f64 aa bgk: {head['mlups']:.0f} MLUPS, {head['algorithmic_gbs']:.0f} GB/s", file=sys.stderr, flush=True)

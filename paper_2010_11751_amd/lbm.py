@@ -16,7 +16,8 @@ from dataclasses import dataclass
 import torch  # loads the HIP runtime the library then binds to
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm.so")
+# LBM_LIBRARY may name another build of the same library (tuning variants).
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(HERE, "liblbm.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 SCHEMES = {"2pop": 0, "swap": 1, "aa": 2}
