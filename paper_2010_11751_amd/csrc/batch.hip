@@ -46,6 +46,10 @@ size_t elem_bytes(int dtype) { return dtype == LBM_F64 ? 8 : dtype == LBM_F32_SH
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 uint32_t grid_for(uint64_t n, int block) { return (uint32_t)((n + block - 1) / block); }
 
+// Padding (elements) around each cavity's streams, covering the largest
+// neighbour offset ny*nz + nz + 1 (the step kernels load speculatively).
+size_t halo_of(const lbm_cavity_desc& d) { return align_up((size_t)d.ny * d.nz + d.nz + 1, 64); }
+
 __global__ void kb_flag_types(uint8_t* fl, int nx, int ny, int nz)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -298,7 +302,7 @@ lbm_batch* lbm_batch_create(int count, const lbm_cavity_desc* d, int scheme, int
     for (int c = 0; c < count; ++c) {
         const uint32_t n = (uint32_t)d[c].nx * d[c].ny * d[c].nz;
         const int64_t stride = (int64_t)align_up(n, 128);
-        const size_t bytes = align_up((size_t)Q * stride * s, 256);
+        const size_t bytes = align_up(((size_t)Q * stride + 2 * halo_of(d[c])) * s, 256);
         off[c] = total;
         total += bytes * (scheme == LBM_2POP ? 2 : 1);
         foff[c] = ftotal;
@@ -327,9 +331,10 @@ lbm_batch* lbm_batch_create(int count, const lbm_cavity_desc* d, int scheme, int
     size_t maxblocks = 0;
     for (int c = 0; c < count; ++c) {
         BatchCavity& B = b->cav[0][c];
-        const size_t bytes = align_up((size_t)Q * B.F.stride * s, 256);
-        B.F.pop = (char*)b->pool + off[c];
-        B.F.out = scheme == LBM_2POP ? (char*)b->pool + off[c] + bytes : nullptr;
+        const size_t bytes = align_up(((size_t)Q * B.F.stride + 2 * halo_of(d[c])) * s, 256);
+        const size_t skip = halo_of(d[c]) * s;
+        B.F.pop = (char*)b->pool + off[c] + skip;
+        B.F.out = scheme == LBM_2POP ? (char*)b->pool + off[c] + bytes + skip : nullptr;
         B.F.flags = b->flags + foff[c];
         b->cav[1][c] = B;
         std::swap(b->cav[1][c].F.pop, b->cav[1][c].F.out);
@@ -418,7 +423,7 @@ int lbm_batch_step_sequential(lbm_batch* b, int n)
     for (int s = 0; s < n; ++s) {
         for (int c = 0; c < b->count; ++c) {
             Launch L{};
-            L.op = OP_STEP;
+            L.op = OP_STEP_ALL;
             L.model = b->collision;
             L.layout = LAYOUT_SOA;
             L.block = b->block;

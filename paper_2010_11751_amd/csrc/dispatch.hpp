@@ -22,6 +22,34 @@ hipError_t launch_step_kind(const Launch& L, hipStream_t s)
 }
 
 template <int Q, int MODEL, class ST, int LAYOUT>
+hipError_t launch_all_kind(const Launch& L, hipStream_t s)
+{
+    const dim3 g(L.grid), b(L.block);
+    switch (L.kind) {
+    case KIND_2POP: k_step_all<Q, MODEL, ST, LAYOUT, KIND_2POP><<<g, b, 0, s>>>(L.F, L.relax); break;
+    case KIND_AA_EVEN: k_step_all<Q, MODEL, ST, LAYOUT, KIND_AA_EVEN><<<g, b, 0, s>>>(L.F, L.relax); break;
+    case KIND_AA_ODD: k_step_all<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, 0, s>>>(L.F, L.relax); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int Q, int MODEL, class ST, int LAYOUT>
+hipError_t launch_slow_kind(const Launch& L, hipStream_t s)
+{
+    const dim3 g(L.grid), b(L.block);
+    switch (L.kind) {
+    case KIND_2POP: k_step_slow<Q, MODEL, ST, LAYOUT, KIND_2POP><<<g, b, 0, s>>>(L.F, L.relax, L.slow_list, L.n_slow); break;
+    case KIND_SWAP_STREAM:
+        k_step_slow<Q, BGK, ST, LAYOUT, KIND_SWAP_STREAM><<<g, b, 0, s>>>(L.F, L.relax, L.slow_list, L.n_slow);
+        break;
+    case KIND_AA_ODD: k_step_slow<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, 0, s>>>(L.F, L.relax, L.slow_list, L.n_slow); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int Q, int MODEL, class ST, int LAYOUT>
 hipError_t launch_batch_kind(const Launch& L, hipStream_t s)
 {
     const dim3 g(L.grid), b(L.block);
@@ -40,6 +68,10 @@ hipError_t launch_model(const Launch& L, hipStream_t s)
     const dim3 g(L.grid), b(L.block);
     switch (L.op) {
     case OP_STEP: return launch_step_kind<Q, MODEL, ST, LAYOUT>(L, s);
+    case OP_STEP_SLOW: return launch_slow_kind<Q, MODEL, ST, LAYOUT>(L, s);
+    case OP_STEP_ALL:
+        if constexpr (Q == 19 && LAYOUT == LAYOUT_SOA) return launch_all_kind<Q, MODEL, ST, LAYOUT>(L, s);
+        else return hipErrorInvalidValue;
     case OP_STEP_BATCH:
         if constexpr (Q == 19 && LAYOUT == LAYOUT_SOA) return launch_batch_kind<Q, MODEL, ST, LAYOUT>(L, s);
         else return hipErrorInvalidValue;

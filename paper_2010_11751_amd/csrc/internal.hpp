@@ -66,7 +66,8 @@ struct BatchCavity {
 
 // A launch request handled by the kernel translation unit of (Q, storage).
 enum Op { OP_STEP = 0, OP_GET = 1, OP_MACRO = 2, OP_SET = 3, OP_INIT = 4, OP_INVARIANTS = 5, OP_NEIGHBORS = 6,
-          OP_STEP_BATCH = 7, OP_GET_CELLS = 8 };
+          OP_STEP_BATCH = 7, OP_GET_CELLS = 8, OP_STEP_SLOW = 9,
+          OP_STEP_ALL = 10 };
 
 struct Launch {
     int op;
@@ -85,6 +86,8 @@ struct Launch {
     int n;
     const BatchCavity* cav;  // STEP_BATCH
     const uint32_t* tiles;
+    const uint32_t* slow_list;  // STEP_SLOW: fluid cells off the fast path
+    uint32_t n_slow;
 };
 
 hipError_t launch_q19_f64(const Launch& L, hipStream_t s);

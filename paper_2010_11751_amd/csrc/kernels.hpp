@@ -37,35 +37,61 @@ using real_t = typename ST::R;
 #define LBM_XCD_REMAP 0
 #endif
 
+// Population accessor. SoA addresses are formed as a wave-uniform 64-bit
+// base (array + k * stride + shift, kept in scalar registers) plus one 32-bit
+// lane offset i * sizeof(T) shared by every stream, so the 19 or 27 streams
+// of a cell cost a single address register. The SoA array carries a halo of
+// padding around its streams (see the runtime), so a shifted access i + d for
+// any cell of the box stays inside the allocation; lanes that will not store
+// may therefore load speculatively without clamping.
 template <class ST, int LAYOUT, int Q, bool STREAM = false>
 struct Acc {
     using T = typename ST::T;
     T* base;
     int64_t stride;
-    __device__ __forceinline__ T* ptr(uint32_t i, int k) const
+    __device__ __forceinline__ T* ptr_shift(uint32_t i, int k, int64_t d) const
     {
-        if constexpr (LAYOUT == LAYOUT_SOA) return base + (size_t)k * (size_t)stride + i;
-        else return base + (size_t)i * Q + k;
+        if constexpr (LAYOUT == LAYOUT_SOA) {
+            char* b = reinterpret_cast<char*>(base + (int64_t)k * stride + d);
+            return reinterpret_cast<T*>(b + (uint32_t)(i * (uint32_t)sizeof(T)));
+        } else {
+            return base + ((int64_t)i + d) * Q + k;
+        }
     }
-    __device__ __forceinline__ real_t<ST> ld(uint32_t i, int k) const
+    __device__ __forceinline__ T* ptr(uint32_t i, int k) const { return ptr_shift(i, k, 0); }
+    __device__ __forceinline__ real_t<ST> ld(uint32_t i, int k) const { return real_t<ST>(raw_ld(i, k)); }
+    __device__ __forceinline__ void st(uint32_t i, int k, real_t<ST> v) const { raw_st(i, k, T(v)); }
+    __device__ __forceinline__ T raw_ld(uint32_t i, int k) const { return raw_ld_shift(i, k, 0); }
+    __device__ __forceinline__ void raw_st(uint32_t i, int k, T v) const { raw_st_shift(i, k, 0, v); }
+    __device__ __forceinline__ T raw_ld_shift(uint32_t i, int k, int64_t d) const
     {
-        if constexpr (STREAM && LBM_NT_LOADS) return real_t<ST>(__builtin_nontemporal_load(ptr(i, k)));
-        else return real_t<ST>(*ptr(i, k));
+        if constexpr (STREAM && LBM_NT_LOADS) return __builtin_nontemporal_load(ptr_shift(i, k, d));
+        else return *ptr_shift(i, k, d);
     }
-    __device__ __forceinline__ void st(uint32_t i, int k, real_t<ST> v) const
+    __device__ __forceinline__ void raw_st_shift(uint32_t i, int k, int64_t d, T v) const
     {
-        if constexpr (STREAM && LBM_NT_STORES) __builtin_nontemporal_store(T(v), ptr(i, k));
-        else *ptr(i, k) = T(v);
+        if constexpr (STREAM && LBM_NT_STORES) __builtin_nontemporal_store(v, ptr_shift(i, k, d));
+        else *ptr_shift(i, k, d) = v;
     }
-    __device__ __forceinline__ T raw_ld(uint32_t i, int k) const
+    // Speculative load at i + d for the fast path: SoA relies on the halo;
+    // AoS (no halo) clamps the cell index into the box.
+    __device__ __forceinline__ real_t<ST> ld_fast(uint32_t i, int k, int64_t d, uint32_t ntot) const
     {
-        if constexpr (STREAM && LBM_NT_LOADS) return __builtin_nontemporal_load(ptr(i, k));
-        else return *ptr(i, k);
+        if constexpr (LAYOUT == LAYOUT_SOA) {
+            return real_t<ST>(raw_ld_shift(i, k, d));
+        } else {
+            const int64_t j = (int64_t)i + d;
+            return real_t<ST>(raw_ld((uint32_t)(j < 0 ? 0 : (j >= (int64_t)ntot ? ntot - 1 : j)), k));
+        }
     }
-    __device__ __forceinline__ void raw_st(uint32_t i, int k, T v) const
+    __device__ __forceinline__ T raw_ld_fast(uint32_t i, int k, int64_t d, uint32_t ntot) const
     {
-        if constexpr (STREAM && LBM_NT_STORES) __builtin_nontemporal_store(v, ptr(i, k));
-        else *ptr(i, k) = v;
+        if constexpr (LAYOUT == LAYOUT_SOA) {
+            return raw_ld_shift(i, k, d);
+        } else {
+            const int64_t j = (int64_t)i + d;
+            return raw_ld((uint32_t)(j < 0 ? 0 : (j >= (int64_t)ntot ? ntot - 1 : j)), k);
+        }
     }
 };
 
@@ -114,9 +140,9 @@ __device__ __forceinline__ Relax<R> relax_of(const RelaxD& p)
 }
 
 // Loads never wait for the flag byte: every lane issues its population loads
-// at once (neighbour indices are clamped into the array, so lanes of wall
-// cells read harmless values), collides, and only the stores and the
-// bounce-back gather of cells next to walls depend on the flag.
+// at once (lanes of wall cells read harmless values from inside the
+// allocation), collides, and only the stores and the bounce-back gather of
+// cells next to walls depend on the flag.
 // An empty asm that takes the loaded values as operands: the loads must then
 // be issued for every lane before the flag decides anything, instead of being
 // sunk under the flag test (which serialises one memory latency per wave).
@@ -127,56 +153,74 @@ __device__ __forceinline__ void issue_all(R (&g)[Q])
     for (int k = 0; k < Q; ++k) asm volatile("" : "+v"(g[k]));
 }
 
-__device__ __forceinline__ uint32_t clamp_cell(int64_t j, uint32_t ntot)
-{
-    return j < 0 ? 0u : (j >= (int64_t)ntot ? ntot - 1 : (uint32_t)j);
-}
 
-template <int Q, int K, int SIGN>
-__device__ __forceinline__ uint32_t fast_neighbour(const Field& F, uint32_t i)
+// Every step kernel exists in three parts. PART_FAST runs over all cells and
+// updates the fluid cells whose neighbours are all fluid and inside the box
+// (constant offsets, no bounce-back code, few registers). PART_SLOW runs over
+// the list of the other fluid cells (next to a wall or on a periodic face)
+// with the general neighbour and bounce-back logic. PART_ALL does both in one
+// pass (used by the batched ensemble). Each cell touches its own set of
+// memory locations, so the split does not change any result (Sec. 2.3).
+enum Part { PART_ALL = 0, PART_FAST = 1, PART_SLOW = 2 };
+
+template <int PART>
+__device__ __forceinline__ bool take_fast(uint8_t fl)
 {
-    return clamp_cell((int64_t)i + offset<Q, K, SIGN>(F), F.ntot);
+    return (fl & (FL_TYPE | FL_SLOW)) == FL_FLUID;
 }
 
 // ---------------------------------------------------------------------------
 // Double-population scheme (Table 1, row 2Pop): collide pop(x), push
 // out_k(x + c_k) <- f_out_k, or out_kbar(x) <- f_out_k + pop_k(x + c_k) when
 // the neighbour is a wall (whose pop_k holds the momentum-exchange term).
-template <int Q, int MODEL, class ST, int LAYOUT>
-__device__ __forceinline__ void cell_2pop(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
+template <int Q, class ST, int LAYOUT>
+__device__ __forceinline__ void push_2pop_slow(const Field& F, uint32_t i, uint8_t fl, const real_t<ST> (&g)[Q])
 {
     using S = L<Q>;
+    const Acc<ST, LAYOUT, Q, true> src{(typename ST::T*)F.pop, F.stride};
+    const Acc<ST, LAYOUT, Q, true> dst{(typename ST::T*)F.out, F.stride};
+    const bool border = fl & FL_BORDER;
+    const Coord c = border ? cell_coord(i, F) : Coord{0, 0, 0};
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k == S::rest) {
+            dst.st(i, k, g[k]);
+        } else {
+            const uint32_t j = neighbour<Q, k, 1>(F, i, border, c);
+            if (is_fluid(F, j)) dst.st(j, k, g[k]);
+            else dst.st(i, S::opp(k), g[k] + src.ld(j, k));
+        }
+    });
+}
+
+template <int Q, int MODEL, class ST, int LAYOUT, int PART>
+__device__ __forceinline__ void cell_2pop(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
+{
     using R = real_t<ST>;
     const Acc<ST, LAYOUT, Q, true> src{(typename ST::T*)F.pop, F.stride};
     const Acc<ST, LAYOUT, Q, true> dst{(typename ST::T*)F.out, F.stride};
     const uint8_t fl = F.flags[i];
     R g[Q];
     static_for<0, Q>([&](auto K) { g[K] = src.ld(i, K); });
-    issue_all(g);
+    if constexpr (PART != PART_SLOW) issue_all(g);
     collide<Q, MODEL, ST::shifted>(g, p);
-    if ((fl & FL_TYPE) != FL_FLUID) return;
-    if (!(fl & FL_SLOW)) {
-        static_for<0, Q>([&](auto K) {
-            constexpr int k = K;
-            dst.st((uint32_t)((int32_t)i + offset<Q, k, 1>(F)), k, g[k]);
-        });
+    if constexpr (PART == PART_SLOW) {
+        push_2pop_slow<Q, ST, LAYOUT>(F, i, fl, g);
     } else {
-        const bool border = fl & FL_BORDER;
-        const Coord c = border ? cell_coord(i, F) : Coord{0, 0, 0};
-        static_for<0, Q>([&](auto K) {
-            constexpr int k = K;
-            if constexpr (k == S::rest) {
-                dst.st(i, k, g[k]);
-            } else {
-                const uint32_t j = neighbour<Q, k, 1>(F, i, border, c);
-                if (is_fluid(F, j)) dst.st(j, k, g[k]);
-                else dst.st(i, S::opp(k), g[k] + src.ld(j, k));
-            }
-        });
+        if ((fl & FL_TYPE) != FL_FLUID) return;
+        if (!(fl & FL_SLOW)) {
+            static_for<0, Q>([&](auto K) {
+                constexpr int k = K;
+                dst.raw_st_shift(i, k, offset<Q, k, 1>(F), typename ST::T(g[k]));
+            });
+        } else if constexpr (PART == PART_ALL) {
+            push_2pop_slow<Q, ST, LAYOUT>(F, i, fl, g);
+        }
     }
 }
 
 // Swap algorithm, collision sweep (Table 1, row Swap): pop_kbar(x) <- f_out_k.
+// Purely local, so every fluid cell is handled by the fast part.
 template <int Q, int MODEL, class ST, int LAYOUT>
 __device__ __forceinline__ void cell_swap_collide(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
 {
@@ -201,44 +245,57 @@ __device__ __forceinline__ void cell_swap_collide(const Field& F, const Relax<re
 // neighbours) is done here by the fluid cell: pop_k(x) += pop_kbar(x - c_k)
 // when x - c_k is a wall. Every location is touched by exactly one thread.
 template <int Q, class ST, int LAYOUT>
+__device__ __forceinline__ void swap_stream_slow(const Field& F, uint32_t i, uint8_t fl)
+{
+    using S = L<Q>;
+    using T = typename ST::T;
+    const Acc<ST, LAYOUT, Q, true> a{(T*)F.pop, F.stride};
+    const bool border = fl & FL_BORDER;
+    const Coord c = border ? cell_coord(i, F) : Coord{0, 0, 0};
+    static_for<0, S::half>([&](auto K) {
+        constexpr int k = K;
+        const uint32_t j = neighbour<Q, k, 1>(F, i, border, c);
+        if (is_fluid(F, j)) {
+            const T m = *a.ptr(i, S::opp(k));
+            const T t = *a.ptr(j, k);
+            *a.ptr(i, S::opp(k)) = t;
+            *a.ptr(j, k) = m;
+        } else {
+            a.st(i, S::opp(k), a.ld(i, S::opp(k)) + a.ld(j, k));
+        }
+        const uint32_t s = neighbour<Q, k, -1>(F, i, border, c);
+        if (!is_fluid(F, s)) a.st(i, k, a.ld(i, k) + a.ld(s, S::opp(k)));
+    });
+}
+
+template <int Q, class ST, int LAYOUT, int PART>
 __device__ __forceinline__ void cell_swap_stream(const Field& F, uint32_t i)
 {
     using S = L<Q>;
     using T = typename ST::T;
     const Acc<ST, LAYOUT, Q, true> a{(T*)F.pop, F.stride};
     const uint8_t fl = F.flags[i];
-    T mine[S::half], theirs[S::half];
-    static_for<0, S::half>([&](auto K) {
-        constexpr int k = K;
-        mine[k] = a.raw_ld(i, S::opp(k));
-        theirs[k] = a.raw_ld(fast_neighbour<Q, k, 1>(F, i), k);
-    });
-    issue_all(mine);
-    issue_all(theirs);
-    if ((fl & FL_TYPE) != FL_FLUID) return;
-    if (!(fl & FL_SLOW)) {
-        static_for<0, S::half>([&](auto K) {
-            constexpr int k = K;
-            a.raw_st(i, S::opp(k), theirs[k]);
-            a.raw_st((uint32_t)((int32_t)i + offset<Q, k, 1>(F)), k, mine[k]);
-        });
+    if constexpr (PART == PART_SLOW) {
+        swap_stream_slow<Q, ST, LAYOUT>(F, i, fl);
     } else {
-        const bool border = fl & FL_BORDER;
-        const Coord c = border ? cell_coord(i, F) : Coord{0, 0, 0};
+        T mine[S::half], theirs[S::half];
         static_for<0, S::half>([&](auto K) {
             constexpr int k = K;
-            const uint32_t j = neighbour<Q, k, 1>(F, i, border, c);
-            if (is_fluid(F, j)) {
-                const T m = *a.ptr(i, S::opp(k));
-                const T t = *a.ptr(j, k);
-                *a.ptr(i, S::opp(k)) = t;
-                *a.ptr(j, k) = m;
-            } else {
-                a.st(i, S::opp(k), a.ld(i, S::opp(k)) + a.ld(j, k));
-            }
-            const uint32_t s = neighbour<Q, k, -1>(F, i, border, c);
-            if (!is_fluid(F, s)) a.st(i, k, a.ld(i, k) + a.ld(s, S::opp(k)));
+            mine[k] = a.raw_ld(i, S::opp(k));
+            theirs[k] = a.raw_ld_fast(i, k, offset<Q, k, 1>(F), F.ntot);
         });
+        issue_all(mine);
+        issue_all(theirs);
+        if ((fl & FL_TYPE) != FL_FLUID) return;
+        if (!(fl & FL_SLOW)) {
+            static_for<0, S::half>([&](auto K) {
+                constexpr int k = K;
+                a.raw_st(i, S::opp(k), theirs[k]);
+                a.raw_st_shift(i, k, offset<Q, k, 1>(F), mine[k]);
+            });
+        } else if constexpr (PART == PART_ALL) {
+            swap_stream_slow<Q, ST, LAYOUT>(F, i, fl);
+        }
     }
 }
 
@@ -255,62 +312,77 @@ __device__ __forceinline__ void cell_aa_even(const Field& F, const Relax<real_t<
 // Push: pop_k(x + c_k) <- f_out_k, or pop_kbar(x) <- f_out_k + pop_k(x + c_k)
 // across a wall. A cell writes exactly the locations it read.
 template <int Q, int MODEL, class ST, int LAYOUT>
+__device__ __forceinline__ void aa_odd_slow(const Field& F, const Relax<real_t<ST>>& p, uint32_t i, uint8_t fl)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    const Acc<ST, LAYOUT, Q, true> a{(typename ST::T*)F.pop, F.stride};
+    const bool border = fl & FL_BORDER;
+    const Coord c = border ? cell_coord(i, F) : Coord{0, 0, 0};
+    R g[Q];
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k == S::rest) {
+            g[k] = a.ld(i, k);
+        } else {
+            const uint32_t s = neighbour<Q, k, -1>(F, i, border, c);
+            if (is_fluid(F, s)) g[k] = a.ld(s, S::opp(k));
+            else g[k] = a.ld(i, k) + a.ld(s, S::opp(k));
+        }
+    });
+    collide<Q, MODEL, ST::shifted>(g, p);
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k == S::rest) {
+            a.st(i, k, g[k]);
+        } else {
+            const uint32_t j = neighbour<Q, k, 1>(F, i, border, c);
+            if (is_fluid(F, j)) a.st(j, k, g[k]);
+            else a.st(i, S::opp(k), g[k] + a.ld(j, k));
+        }
+    });
+}
+
+template <int Q, int MODEL, class ST, int LAYOUT, int PART>
 __device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
 {
     using S = L<Q>;
     using R = real_t<ST>;
     const Acc<ST, LAYOUT, Q, true> a{(typename ST::T*)F.pop, F.stride};
     const uint8_t fl = F.flags[i];
-    R g[Q];
-    static_for<0, Q>([&](auto K) {
-        constexpr int k = K;
-        if constexpr (k == S::rest) g[k] = a.ld(i, k);
-        else g[k] = a.ld(fast_neighbour<Q, k, -1>(F, i), S::opp(k));
-    });
-    issue_all(g);
-    const bool fluid = (fl & FL_TYPE) == FL_FLUID;
-    const bool slow = fluid && (fl & FL_SLOW);
-    const bool border = fl & FL_BORDER;
-    const Coord c = (slow && border) ? cell_coord(i, F) : Coord{0, 0, 0};
-    if (slow) {
-        static_for<0, Q>([&](auto K) {
-            constexpr int k = K;
-            if constexpr (k != S::rest) {
-                const uint32_t s = neighbour<Q, k, -1>(F, i, border, c);
-                if (is_fluid(F, s)) g[k] = a.ld(s, S::opp(k));
-                else g[k] = a.ld(i, k) + a.ld(s, S::opp(k));
-            }
-        });
-    }
-    collide<Q, MODEL, ST::shifted>(g, p);
-    if (!fluid) return;
-    if (!slow) {
-        static_for<0, Q>([&](auto K) {
-            constexpr int k = K;
-            a.st((uint32_t)((int32_t)i + offset<Q, k, 1>(F)), k, g[k]);
-        });
+    if constexpr (PART == PART_SLOW) {
+        aa_odd_slow<Q, MODEL, ST, LAYOUT>(F, p, i, fl);
     } else {
+        if constexpr (PART == PART_ALL) {
+            if ((fl & FL_TYPE) == FL_FLUID && (fl & FL_SLOW)) {
+                aa_odd_slow<Q, MODEL, ST, LAYOUT>(F, p, i, fl);
+                return;
+            }
+        }
+        R g[Q];
         static_for<0, Q>([&](auto K) {
             constexpr int k = K;
-            if constexpr (k == S::rest) {
-                a.st(i, k, g[k]);
-            } else {
-                const uint32_t j = neighbour<Q, k, 1>(F, i, border, c);
-                if (is_fluid(F, j)) a.st(j, k, g[k]);
-                else a.st(i, S::opp(k), g[k] + a.ld(j, k));
-            }
+            if constexpr (k == S::rest) g[k] = a.ld(i, k);
+            else g[k] = a.ld_fast(i, S::opp(k), offset<Q, k, -1>(F), F.ntot);
+        });
+        issue_all(g);
+        collide<Q, MODEL, ST::shifted>(g, p);
+        if (!take_fast<PART>(fl)) return;
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            a.raw_st_shift(i, k, offset<Q, k, 1>(F), typename ST::T(g[k]));
         });
     }
 }
 
-template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
+template <int Q, int MODEL, class ST, int LAYOUT, int KIND, int PART>
 __device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
 {
-    if constexpr (KIND == KIND_2POP) cell_2pop<Q, MODEL, ST, LAYOUT>(F, p, i);
+    if constexpr (KIND == KIND_2POP) cell_2pop<Q, MODEL, ST, LAYOUT, PART>(F, p, i);
     else if constexpr (KIND == KIND_SWAP_COLLIDE) cell_swap_collide<Q, MODEL, ST, LAYOUT>(F, p, i);
-    else if constexpr (KIND == KIND_SWAP_STREAM) cell_swap_stream<Q, ST, LAYOUT>(F, i);
+    else if constexpr (KIND == KIND_SWAP_STREAM) cell_swap_stream<Q, ST, LAYOUT, PART>(F, i);
     else if constexpr (KIND == KIND_AA_EVEN) cell_aa_even<Q, MODEL, ST, LAYOUT>(F, p, i);
-    else cell_aa_odd<Q, MODEL, ST, LAYOUT>(F, p, i);
+    else cell_aa_odd<Q, MODEL, ST, LAYOUT, PART>(F, p, i);
 }
 
 __device__ __forceinline__ uint32_t step_block()
@@ -323,12 +395,46 @@ __device__ __forceinline__ uint32_t step_block()
     return b;
 }
 
+// Minimum waves per SIMD the compiler must fit the fast step kernels into
+// (0: compiler's choice).
+#ifndef LBM_WAVES_PER_EU
+#define LBM_WAVES_PER_EU 0
+#endif
+#if LBM_WAVES_PER_EU > 0
+#define LBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
+#else
+#define LBM_STEP_ATTR
+#endif
+
+// Fast part over every cell of the lattice.
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
-__global__ void __launch_bounds__(1024) k_step(Field F, RelaxD pd)
+__global__ void __launch_bounds__(1024) LBM_STEP_ATTR k_step(Field F, RelaxD pd)
 {
     const uint32_t i = step_block() * blockDim.x + threadIdx.x;
     if (i >= F.ntot) return;
-    cell_step<Q, MODEL, ST, LAYOUT, KIND>(F, relax_of<real_t<ST>>(pd), i);
+    cell_step<Q, MODEL, ST, LAYOUT, KIND, PART_FAST>(F, relax_of<real_t<ST>>(pd), i);
+}
+
+// Fast and slow parts in one pass over every cell (one launch per step, as
+// the per-cavity reference path of the batched ensemble uses).
+template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
+__global__ void __launch_bounds__(1024) k_step_all(Field F, RelaxD pd)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F.ntot) return;
+    cell_step<Q, MODEL, ST, LAYOUT, KIND, PART_ALL>(F, relax_of<real_t<ST>>(pd), i);
+}
+
+// Slow part over the listed cells (fluid cells next to a wall or on a
+// periodic face); only the kinds that touch neighbours have one.
+template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
+__global__ void __launch_bounds__(256) k_step_slow(Field F, RelaxD pd, const uint32_t* __restrict__ list, uint32_t n)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t i = list[j];
+    if (i >= F.ntot) return;
+    cell_step<Q, MODEL, ST, LAYOUT, KIND, PART_SLOW>(F, relax_of<real_t<ST>>(pd), i);
 }
 
 // ---------------------------------------------------------------------------
@@ -342,7 +448,7 @@ __global__ void __launch_bounds__(1024) k_step_batch(const BatchCavity* __restri
     const BatchCavity& B = cav[c];
     const uint32_t i = (t & 0xffffu) * blockDim.x + threadIdx.x;
     if (i >= B.F.ntot) return;
-    cell_step<Q, MODEL, ST, LAYOUT, KIND>(B.F, relax_of<real_t<ST>>(B.relax), i);
+    cell_step<Q, MODEL, ST, LAYOUT, KIND, PART_ALL>(B.F, relax_of<real_t<ST>>(B.relax), i);
 }
 
 // ---------------------------------------------------------------------------

@@ -73,6 +73,15 @@ int64_t soa_stride(int64_t ntot)
     return s;
 }
 
+// SoA halo: padding (elements) before the first and after the last stream,
+// at least the largest neighbour offset ny*nz + nz + 1, so that a shifted
+// access i +- d_k of any cell stays inside the allocation.
+int64_t soa_halo(int ny, int nz)
+{
+    const int64_t h = (int64_t)ny * nz + nz + 1;
+    return (h + 255) / 256 * 256;
+}
+
 double trt_omega_minus(double omega, double lambda)
 {
     return 1.0 / (0.5 + lambda / (1.0 / omega - 0.5));
@@ -177,7 +186,9 @@ struct lbm_handle {
     int q = 19;
     int64_t ntot = 0, fluid = 0, stride = 0;
     size_t pop_bytes = 0, out_bytes = 0, flag_bytes = 0;
-    void* pop = nullptr;
+    void* pop_alloc = nullptr;  // allocations (or caller buffers) as given
+    void* out_alloc = nullptr;
+    void* pop = nullptr;        // cell 0 of stream 0 (past the SoA halo)
     void* out = nullptr;
     uint8_t* flags = nullptr;
     bool own_pop = false, own_out = false, own_flags = false;
@@ -189,6 +200,8 @@ struct lbm_handle {
     int block = 256;
     double* partial = nullptr;  // invariant partial sums (2 per block) + 2 results
     int red_blocks = 0;
+    uint32_t* slow_list = nullptr;  // fluid cells off the fast path, ascending
+    uint32_t n_slow = 0;
     LaunchFn launch = nullptr;
 
     Field field() const
@@ -248,6 +261,8 @@ static int validate(const lbm_desc* d)
     if (d->geometry == LBM_CHANNEL && d->nz < 3) return fail(LBM_EINVAL, "channel needs nz >= 3");
     const int64_t n = (int64_t)d->nx * d->ny * d->nz;
     if (n > 0x7fffffffLL) return fail(LBM_EUNSUPPORTED, "more than 2^31-1 cells");
+    if (d->layout == LBM_SOA && (uint64_t)n * elem_bytes(d->storage_dtype) >= (1ull << 32))
+        return fail(LBM_EUNSUPPORTED, "SoA streams above 4 GiB (cells x bytes per value) are not supported");
     if (d->scheme < LBM_2POP || d->scheme > LBM_AA) return fail(LBM_EINVAL, "unknown scheme");
     if (d->collision < LBM_BGK || d->collision > LBM_RR) return fail(LBM_EINVAL, "unknown collision model");
     if (d->storage_dtype < LBM_F64 || d->storage_dtype > LBM_F16_SHIFTED) return fail(LBM_EINVAL, "unknown storage dtype");
@@ -273,7 +288,9 @@ int lbm_required_bytes(const lbm_desc* d, size_t out[3])
     if (!out) return fail(LBM_EINVAL, "null output");
     const int64_t n = (int64_t)d->nx * d->ny * d->nz;
     const size_t s = elem_bytes(d->storage_dtype);
-    const size_t pop = d->layout == LBM_SOA ? (size_t)soa_stride(n) * d->lattice * s : (size_t)n * d->lattice * s;
+    const size_t pop = d->layout == LBM_SOA
+                           ? ((size_t)soa_stride(n) * d->lattice + 2 * (size_t)soa_halo(d->ny, d->nz)) * s
+                           : (size_t)n * d->lattice * s;
     out[0] = pop;
     out[1] = d->scheme == LBM_2POP ? pop : 0;
     out[2] = (size_t)n;
@@ -301,25 +318,40 @@ static int init_state(lbm_handle* h, const double* rho, const double* u)
     return LBM_OK;
 }
 
+// One kernel kind over the lattice: the fast part over all cells, then, for
+// the kinds that reach neighbours, the slow part over the listed cells.
+static int run_kind(lbm_handle* h, int kind)
+{
+    Launch L = h->base(OP_STEP);
+    L.kind = kind;
+    int rc = run(h, L);
+    if (rc) return rc;
+    const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD;
+    if (neighbours && h->n_slow > 0) {
+        L.op = OP_STEP_SLOW;
+        L.block = 256;
+        L.grid = grid_for(h->n_slow, 256);
+        L.slow_list = h->slow_list;
+        L.n_slow = h->n_slow;
+        rc = run(h, L);
+    }
+    return rc;
+}
+
 static int enqueue_steps(lbm_handle* h, int n)
 {
     for (int s = 0; s < n; ++s) {
-        Launch L = h->base(OP_STEP);
+        int rc;
         if (h->d.scheme == LBM_2POP) {
-            L.kind = KIND_2POP;
-            int rc = run(h, L);
+            rc = run_kind(h, KIND_2POP);
             if (rc) return rc;
             std::swap(h->pop, h->out);
         } else if (h->d.scheme == LBM_SWAP) {
-            L.kind = KIND_SWAP_COLLIDE;
-            int rc = run(h, L);
-            if (rc) return rc;
-            L.kind = KIND_SWAP_STREAM;
-            rc = run(h, L);
+            rc = run_kind(h, KIND_SWAP_COLLIDE);
+            if (!rc) rc = run_kind(h, KIND_SWAP_STREAM);
             if (rc) return rc;
         } else {
-            L.kind = h->aa_phase ? KIND_AA_ODD : KIND_AA_EVEN;
-            int rc = run(h, L);
+            rc = run_kind(h, h->aa_phase ? KIND_AA_ODD : KIND_AA_EVEN);
             if (rc) return rc;
             h->aa_phase ^= 1;
         }
@@ -380,10 +412,11 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
 
     auto bail = [&](int code, const std::string& msg) -> lbm_handle* {
         fail(code, msg);
-        if (h->own_pop && h->pop) hipFree(h->pop);
-        if (h->own_out && h->out) hipFree(h->out);
+        if (h->own_pop && h->pop_alloc) hipFree(h->pop_alloc);
+        if (h->own_out && h->out_alloc) hipFree(h->out_alloc);
         if (h->own_flags && h->flags) hipFree(h->flags);
         if (h->partial) hipFree(h->partial);
+        if (h->slow_list) hipFree(h->slow_list);
         delete h;
         return nullptr;
     };
@@ -396,19 +429,24 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
         }
         return true;
     };
-    if (d->pop) h->pop = d->pop;
-    else if (alloc(&h->pop, h->pop_bytes, "pop")) h->own_pop = true;
+    if (d->pop) h->pop_alloc = d->pop;
+    else if (alloc(&h->pop_alloc, h->pop_bytes, "pop")) h->own_pop = true;
     else return bail(LBM_ENOMEM, lbm_last_error());
     if (d->scheme == LBM_2POP) {
-        if (d->out) h->out = d->out;
-        else if (alloc(&h->out, h->out_bytes, "out")) h->own_out = true;
+        if (d->out) h->out_alloc = d->out;
+        else if (alloc(&h->out_alloc, h->out_bytes, "out")) h->own_out = true;
         else return bail(LBM_ENOMEM, lbm_last_error());
     }
     if (d->flags) h->flags = (uint8_t*)d->flags;
     else if (alloc((void**)&h->flags, h->flag_bytes, "flags")) h->own_flags = true;
     else return bail(LBM_ENOMEM, lbm_last_error());
-    for (void* p : {h->pop, h->out, (void*)h->flags})
+    for (void* p : {h->pop_alloc, h->out_alloc, (void*)h->flags})
         if (p && ((uintptr_t)p % 256) != 0) return bail(LBM_EINVAL, "caller buffers must be 256-byte aligned");
+    {
+        const size_t skip = d->layout == LBM_SOA ? (size_t)soa_halo(d->ny, d->nz) * elem_bytes(d->storage_dtype) : 0;
+        h->pop = (char*)h->pop_alloc + skip;
+        h->out = h->out_alloc ? (char*)h->out_alloc + skip : nullptr;
+    }
 
     h->red_blocks = (int)grid_for((uint64_t)h->ntot, 256);
     if (!alloc((void**)&h->partial, sizeof(double) * (2 * (size_t)h->red_blocks + 2), "reduction"))
@@ -426,6 +464,24 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("flag set-up: ") + hipGetErrorString(e));
     h->fluid = (int64_t)nf;
+
+    // Fluid cells that need the general neighbour / bounce-back path, in
+    // ascending order.
+    {
+        std::vector<uint8_t> fl((size_t)h->ntot);
+        e = hipMemcpy(fl.data(), h->flags, (size_t)h->ntot, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("flag read-back: ") + hipGetErrorString(e));
+        std::vector<uint32_t> slow;
+        for (int64_t i = 0; i < h->ntot; ++i)
+            if ((fl[i] & FL_TYPE) == FL_FLUID && (fl[i] & FL_SLOW)) slow.push_back((uint32_t)i);
+        h->n_slow = (uint32_t)slow.size();
+        if (h->n_slow) {
+            if (!alloc((void**)&h->slow_list, sizeof(uint32_t) * slow.size(), "slow list"))
+                return bail(LBM_ENOMEM, lbm_last_error());
+            e = hipMemcpy(h->slow_list, slow.data(), sizeof(uint32_t) * slow.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("slow list: ") + hipGetErrorString(e));
+        }
+    }
 
     if (init_state(h, nullptr, nullptr)) return bail(LBM_EDEVICE, lbm_last_error());
     if (d->block_size == -1) {
@@ -458,10 +514,11 @@ void lbm_destroy(lbm_handle* h)
     if (!h) return;
     if (h->stream) hipStreamSynchronize(h->stream);
     else hipDeviceSynchronize();
-    if (h->own_pop && h->pop) hipFree(h->pop);
-    if (h->own_out && h->out) hipFree(h->out);
+    if (h->own_pop && h->pop_alloc) hipFree(h->pop_alloc);
+    if (h->own_out && h->out_alloc) hipFree(h->out_alloc);
     if (h->own_flags && h->flags) hipFree(h->flags);
     if (h->partial) hipFree(h->partial);
+    if (h->slow_list) hipFree(h->slow_list);
     delete h;
 }
 
