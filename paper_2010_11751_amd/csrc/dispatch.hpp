@@ -10,6 +10,18 @@ template <int Q, int MODEL, class ST, int LAYOUT>
 hipError_t launch_step_kind(const Launch& L, hipStream_t s)
 {
     const dim3 g(L.grid), b(L.block);
+    constexpr int CPT = cells_per_thread((int)sizeof(typename ST::T));
+    if constexpr (CPT > 1 && LAYOUT == LAYOUT_SOA) {
+        switch (L.kind) {
+        case KIND_2POP: k_step_vec<Q, MODEL, ST, KIND_2POP, CPT><<<g, b, 0, s>>>(L.F, L.relax); break;
+        case KIND_SWAP_COLLIDE: k_step_vec<Q, MODEL, ST, KIND_SWAP_COLLIDE, CPT><<<g, b, 0, s>>>(L.F, L.relax); break;
+        case KIND_SWAP_STREAM: k_step_vec<Q, BGK, ST, KIND_SWAP_STREAM, CPT><<<g, b, 0, s>>>(L.F, L.relax); break;
+        case KIND_AA_EVEN: k_step_vec<Q, MODEL, ST, KIND_AA_EVEN, CPT><<<g, b, 0, s>>>(L.F, L.relax); break;
+        case KIND_AA_ODD: k_step_vec<Q, MODEL, ST, KIND_AA_ODD, CPT><<<g, b, 0, s>>>(L.F, L.relax); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (L.kind) {
     case KIND_2POP: k_step<Q, MODEL, ST, LAYOUT, KIND_2POP><<<g, b, 0, s>>>(L.F, L.relax); break;
     case KIND_SWAP_COLLIDE: k_step<Q, MODEL, ST, LAYOUT, KIND_SWAP_COLLIDE><<<g, b, 0, s>>>(L.F, L.relax); break;
@@ -44,6 +56,10 @@ hipError_t launch_slow_kind(const Launch& L, hipStream_t s)
         k_step_slow<Q, BGK, ST, LAYOUT, KIND_SWAP_STREAM><<<g, b, 0, s>>>(L.F, L.relax, L.slow_list, L.n_slow);
         break;
     case KIND_AA_ODD: k_step_slow<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, 0, s>>>(L.F, L.relax, L.slow_list, L.n_slow); break;
+    case KIND_AA_EVEN: k_step_slow<Q, MODEL, ST, LAYOUT, KIND_AA_EVEN><<<g, b, 0, s>>>(L.F, L.relax, L.slow_list, L.n_slow); break;
+    case KIND_SWAP_COLLIDE:
+        k_step_slow<Q, MODEL, ST, LAYOUT, KIND_SWAP_COLLIDE><<<g, b, 0, s>>>(L.F, L.relax, L.slow_list, L.n_slow);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -23,6 +23,15 @@ enum Layout { LAYOUT_SOA = 0, LAYOUT_AOS = 1 };
 enum Kind { KIND_2POP = 0, KIND_SWAP_COLLIDE = 1, KIND_SWAP_STREAM = 2, KIND_AA_EVEN = 3, KIND_AA_ODD = 4 };
 enum Storage { STORE_F64 = 0, STORE_F32 = 1, STORE_F16 = 2 };
 
+// Cells per thread of the fast step kernels: each lane updates this many
+// consecutive cells and moves each population stream as one vector of
+// LBM_VEC_BYTES (0: one cell per lane). Fluid cells of groups that are not
+// entirely on the fast path go to the near-wall list.
+#ifndef LBM_VEC_BYTES
+#define LBM_VEC_BYTES 0
+#endif
+constexpr int cells_per_thread(int elem_bytes) { return LBM_VEC_BYTES > 0 ? LBM_VEC_BYTES / elem_bytes : 1; }
+
 struct StoreF64 {
     using T = double;
     using R = double;

@@ -220,7 +220,11 @@ __device__ __forceinline__ void cell_2pop(const Field& F, const Relax<real_t<ST>
 }
 
 // Swap algorithm, collision sweep (Table 1, row Swap): pop_kbar(x) <- f_out_k.
-// Purely local, so every fluid cell is handled by the fast part.
+// Purely local, so every fluid cell is handled by the fast part. Lanes of
+// wall cells store back the values they loaded (slot k̄ gets its own value),
+// which changes nothing in memory but keeps every store instruction writing
+// whole cache lines: a line left partly unwritten costs a read-modify-write
+// in HBM.
 template <int Q, int MODEL, class ST, int LAYOUT>
 __device__ __forceinline__ void cell_swap_collide(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
 {
@@ -228,14 +232,15 @@ __device__ __forceinline__ void cell_swap_collide(const Field& F, const Relax<re
     using R = real_t<ST>;
     const Acc<ST, LAYOUT, Q, true> a{(typename ST::T*)F.pop, F.stride};
     const uint8_t fl = F.flags[i];
-    R g[Q];
+    R g[Q], keep[Q];
     static_for<0, Q>([&](auto K) { g[K] = a.ld(i, K); });
     issue_all(g);
+    static_for<0, Q>([&](auto K) { keep[K] = g[K]; });
     collide<Q, MODEL, ST::shifted>(g, p);
-    if ((fl & FL_TYPE) != FL_FLUID) return;
+    const bool fluid = (fl & FL_TYPE) == FL_FLUID;
     static_for<0, Q>([&](auto K) {
         constexpr int k = K;
-        a.st(i, S::opp(k), g[k]);
+        a.st(i, S::opp(k), fluid ? g[k] : keep[S::opp(k)]);
     });
 }
 
@@ -413,6 +418,86 @@ __global__ void __launch_bounds__(1024) LBM_STEP_ATTR k_step(Field F, RelaxD pd)
     const uint32_t i = step_block() * blockDim.x + threadIdx.x;
     if (i >= F.ntot) return;
     cell_step<Q, MODEL, ST, LAYOUT, KIND, PART_FAST>(F, relax_of<real_t<ST>>(pd), i);
+}
+
+// ---------------------------------------------------------------------------
+// Fast part with CPT consecutive cells per lane (SoA): every stream access is
+// one CPT-wide vector (aligned to the element, not the vector, since
+// neighbour shifts move it by one element).
+template <class T, int N>
+struct VecOf {
+    typedef T type __attribute__((ext_vector_type(N), aligned(sizeof(T))));
+};
+
+template <int CPT>
+__device__ __forceinline__ bool group_fast(const uint8_t* flags, uint32_t i0)
+{
+    if constexpr (CPT == 2) return (*reinterpret_cast<const uint16_t*>(flags + i0) & 0xC3C3u) == 0;
+    else if constexpr (CPT == 4) return (*reinterpret_cast<const uint32_t*>(flags + i0) & 0xC3C3C3C3u) == 0;
+    else if constexpr (CPT == 8) return (*reinterpret_cast<const uint64_t*>(flags + i0) & 0xC3C3C3C3C3C3C3C3ull) == 0;
+    else return (flags[i0] & (FL_TYPE | FL_SLOW)) == FL_FLUID;
+}
+
+template <int Q, int MODEL, class ST, int KIND, int CPT>
+__device__ __forceinline__ void group_step(const Field& F, const Relax<real_t<ST>>& p, uint32_t i0)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    using T = typename ST::T;
+    using V = typename VecOf<T, CPT>::type;
+    const Acc<ST, LAYOUT_SOA, Q, true> a{(T*)F.pop, F.stride};
+    const Acc<ST, LAYOUT_SOA, Q, true> o{(T*)(KIND == KIND_2POP ? F.out : F.pop), F.stride};
+    const bool fast = group_fast<CPT>(F.flags, i0);
+    if constexpr (KIND == KIND_SWAP_STREAM) {
+        V mine[S::half], theirs[S::half];
+        static_for<0, S::half>([&](auto K) {
+            constexpr int k = K;
+            mine[k] = *reinterpret_cast<const V*>(a.ptr(i0, S::opp(k)));
+            theirs[k] = *reinterpret_cast<const V*>(a.ptr_shift(i0, k, offset<Q, k, 1>(F)));
+        });
+        issue_all(mine);
+        issue_all(theirs);
+        if (!fast) return;
+        static_for<0, S::half>([&](auto K) {
+            constexpr int k = K;
+            *reinterpret_cast<V*>(a.ptr(i0, S::opp(k))) = theirs[k];
+            *reinterpret_cast<V*>(a.ptr_shift(i0, k, offset<Q, k, 1>(F))) = mine[k];
+        });
+    } else {
+        V v[Q];
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            if constexpr (KIND == KIND_AA_ODD && k != S::rest)
+                v[k] = *reinterpret_cast<const V*>(a.ptr_shift(i0, S::opp(k), offset<Q, k, -1>(F)));
+            else
+                v[k] = *reinterpret_cast<const V*>(a.ptr(i0, k));
+        });
+        issue_all(v);
+        V w[Q];
+        static_for<0, CPT>([&](auto C) {
+            constexpr int c = C;
+            R g[Q];
+            static_for<0, Q>([&](auto K) { g[K] = R(v[K][c]); });
+            collide<Q, MODEL, ST::shifted>(g, p);
+            static_for<0, Q>([&](auto K) { w[K][c] = T(g[K]); });
+        });
+        if (!fast) return;
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            if constexpr (KIND == KIND_AA_EVEN || KIND == KIND_SWAP_COLLIDE)
+                *reinterpret_cast<V*>(o.ptr(i0, S::opp(k))) = w[k];
+            else
+                *reinterpret_cast<V*>(o.ptr_shift(i0, k, offset<Q, k, 1>(F))) = w[k];
+        });
+    }
+}
+
+template <int Q, int MODEL, class ST, int KIND, int CPT>
+__global__ void __launch_bounds__(256) LBM_STEP_ATTR k_step_vec(Field F, RelaxD pd)
+{
+    const uint32_t i0 = (step_block() * blockDim.x + threadIdx.x) * CPT;
+    if (i0 + CPT > F.ntot) return;  // a ragged tail is in the near-wall list
+    group_step<Q, MODEL, ST, KIND, CPT>(F, relax_of<real_t<ST>>(pd), i0);
 }
 
 // Fast and slow parts in one pass over every cell (one launch per step, as

@@ -202,6 +202,9 @@ struct lbm_handle {
     int red_blocks = 0;
     uint32_t* slow_list = nullptr;  // fluid cells off the fast path, ascending
     uint32_t n_slow = 0;
+    int cpt = 1;                    // cells per lane of the fast step kernels
+    hipStream_t aux = nullptr;      // runs the near-wall part beside the fast part
+    hipEvent_t fork = nullptr, join = nullptr;
     LaunchFn launch = nullptr;
 
     Field field() const
@@ -324,10 +327,17 @@ static int run_kind(lbm_handle* h, int kind)
 {
     Launch L = h->base(OP_STEP);
     L.kind = kind;
+    const int cpt = h->cpt;
+    if (cpt > 1) {  // the vector kernels are compiled for blocks of at most 256
+        L.block = std::min(h->block, 256);
+        L.grid = grid_for(((uint64_t)h->ntot + cpt - 1) / cpt, L.block);
+    }
     int rc = run(h, L);
     if (rc) return rc;
+    // With several cells per lane the fast part skips whole groups, so the
+    // listed cells need the second launch for the local kinds as well.
     const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD;
-    if (neighbours && h->n_slow > 0) {
+    if ((neighbours || cpt > 1) && h->n_slow > 0) {
         L.op = OP_STEP_SLOW;
         L.block = 256;
         L.grid = grid_for(h->n_slow, 256);
@@ -338,20 +348,51 @@ static int run_kind(lbm_handle* h, int kind)
     return rc;
 }
 
+// The same, with the near-wall part on a second stream so that its scattered,
+// latency-bound accesses overlap the fast part's streaming. Both parts touch
+// disjoint memory (every cell owns its locations), and the handle's stream
+// waits for the second one before the next launch.
+static int run_kind_overlapped(lbm_handle* h, int kind)
+{
+    const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD;
+    if (!h->aux || h->n_slow == 0 || !(neighbours || h->cpt > 1)) return run_kind(h, kind);
+    HIP_TRY(hipEventRecord(h->fork, h->stream), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(h->aux, h->fork, 0), "hipStreamWaitEvent");
+    Launch S = h->base(OP_STEP_SLOW);
+    S.kind = kind;
+    S.block = 256;
+    S.grid = grid_for(h->n_slow, 256);
+    S.slow_list = h->slow_list;
+    S.n_slow = h->n_slow;
+    hipError_t e = h->launch(S, h->aux);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    HIP_TRY(hipEventRecord(h->join, h->aux), "hipEventRecord");
+    Launch L = h->base(OP_STEP);
+    L.kind = kind;
+    if (h->cpt > 1) {
+        L.block = std::min(h->block, 256);
+        L.grid = grid_for(((uint64_t)h->ntot + h->cpt - 1) / h->cpt, L.block);
+    }
+    int rc = run(h, L);
+    if (rc) return rc;
+    HIP_TRY(hipStreamWaitEvent(h->stream, h->join, 0), "hipStreamWaitEvent");
+    return LBM_OK;
+}
+
 static int enqueue_steps(lbm_handle* h, int n)
 {
     for (int s = 0; s < n; ++s) {
         int rc;
         if (h->d.scheme == LBM_2POP) {
-            rc = run_kind(h, KIND_2POP);
+            rc = run_kind_overlapped(h, KIND_2POP);
             if (rc) return rc;
             std::swap(h->pop, h->out);
         } else if (h->d.scheme == LBM_SWAP) {
-            rc = run_kind(h, KIND_SWAP_COLLIDE);
-            if (!rc) rc = run_kind(h, KIND_SWAP_STREAM);
+            rc = run_kind_overlapped(h, KIND_SWAP_COLLIDE);
+            if (!rc) rc = run_kind_overlapped(h, KIND_SWAP_STREAM);
             if (rc) return rc;
         } else {
-            rc = run_kind(h, h->aa_phase ? KIND_AA_ODD : KIND_AA_EVEN);
+            rc = run_kind_overlapped(h, h->aa_phase ? KIND_AA_ODD : KIND_AA_EVEN);
             if (rc) return rc;
             h->aa_phase ^= 1;
         }
@@ -417,6 +458,9 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
         if (h->own_flags && h->flags) hipFree(h->flags);
         if (h->partial) hipFree(h->partial);
         if (h->slow_list) hipFree(h->slow_list);
+        if (h->fork) hipEventDestroy(h->fork);
+        if (h->join) hipEventDestroy(h->join);
+        if (h->aux) hipStreamDestroy(h->aux);
         delete h;
         return nullptr;
     };
@@ -471,9 +515,18 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
         std::vector<uint8_t> fl((size_t)h->ntot);
         e = hipMemcpy(fl.data(), h->flags, (size_t)h->ntot, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("flag read-back: ") + hipGetErrorString(e));
+        h->cpt = d->layout == LBM_SOA ? cells_per_thread((int)elem_bytes(d->storage_dtype)) : 1;
+        const int64_t cpt = h->cpt;
         std::vector<uint32_t> slow;
-        for (int64_t i = 0; i < h->ntot; ++i)
-            if ((fl[i] & FL_TYPE) == FL_FLUID && (fl[i] & FL_SLOW)) slow.push_back((uint32_t)i);
+        for (int64_t g0 = 0; g0 < h->ntot; g0 += cpt) {
+            // a group is fast when it is whole and every cell in it is a fast fluid cell
+            bool fast = g0 + cpt <= h->ntot;
+            for (int64_t i = g0; i < g0 + cpt && i < h->ntot; ++i)
+                fast = fast && (fl[i] & (FL_TYPE | FL_SLOW)) == FL_FLUID;
+            if (fast) continue;
+            for (int64_t i = g0; i < g0 + cpt && i < h->ntot; ++i)
+                if ((fl[i] & FL_TYPE) == FL_FLUID) slow.push_back((uint32_t)i);
+        }
         h->n_slow = (uint32_t)slow.size();
         if (h->n_slow) {
             if (!alloc((void**)&h->slow_list, sizeof(uint32_t) * slow.size(), "slow list"))
@@ -483,6 +536,12 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
         }
     }
 
+    if (h->n_slow > 0 && !std::getenv("LBM_NO_OVERLAP")) {
+        e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join, hipEventDisableTiming);
+        if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("auxiliary stream: ") + hipGetErrorString(e));
+    }
     if (init_state(h, nullptr, nullptr)) return bail(LBM_EDEVICE, lbm_last_error());
     if (d->block_size == -1) {
         if (autotune(h) || init_state(h, nullptr, nullptr)) return bail(LBM_EDEVICE, lbm_last_error());
@@ -514,11 +573,15 @@ void lbm_destroy(lbm_handle* h)
     if (!h) return;
     if (h->stream) hipStreamSynchronize(h->stream);
     else hipDeviceSynchronize();
+    if (h->aux) hipStreamSynchronize(h->aux);
     if (h->own_pop && h->pop_alloc) hipFree(h->pop_alloc);
     if (h->own_out && h->out_alloc) hipFree(h->out_alloc);
     if (h->own_flags && h->flags) hipFree(h->flags);
     if (h->partial) hipFree(h->partial);
     if (h->slow_list) hipFree(h->slow_list);
+    if (h->fork) hipEventDestroy(h->fork);
+    if (h->join) hipEventDestroy(h->join);
+    if (h->aux) hipStreamDestroy(h->aux);
     delete h;
 }
 
