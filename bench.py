@@ -111,6 +111,96 @@ def run_case(scheme, coll, dtype, steps, warmup, cav):
     }
 
 
+def run_d3q27_rr(steps, warmup):
+    """512^3 D3Q27 cavity, recursive regularized, FP32-shifted AA (Re 5000)."""
+    from paper_2010_11751_amd import lbm, workloads as W
+    cav = W.CAVITY_512
+    sim = lbm.Lattice(27, cav.n, scheme="aa", collision="rr", omega=cav.omega, u_lid=cav.u_lid, dtype="f32")
+    info = sim.info()
+    ms, _ = time_steps(sim, steps, warmup)
+    m, e = sim.invariants()
+    sim.close()
+    gbs = info.fluid_cells * info.bytes_per_update / (ms * 1e-3) / 1e9
+    return {"workload": "D3Q27 lid-driven cavity 512^3, RR, FP32-shifted AA-SoA, Re=5000, u_lid=0.05",
+            "mlups": round(info.fluid_cells / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+            "bytes_per_update": info.bytes_per_update, "hbm_gbs": round(gbs, 1),
+            "roofline_frac": round(gbs / PEAK_HBM_GBS, 4), "steps": steps, "finite": bool(m == m and e == e)}
+
+
+def run_taylor_green(steps):
+    """256^3 periodic Taylor-Green vortex (u0 = 0.04, nu = 0.01), BGK AA-SoA,
+    FP64 vs FP32- and FP16-shifted storage: MLUPS, velocity relative L2
+    against the FP64 run, and the decay of the (k,k,k) mode against
+    exp(-3 nu k^2 t)."""
+    import math
+    import torch
+    from paper_2010_11751_amd import lbm, workloads as W
+    n = W.TGV_N
+    omega = W.omega_from_nu(W.TGV_NU)
+    u0 = torch.from_numpy(W.taylor_green_velocity(n, n, n, W.TGV_U0))
+    mode = u0[0].to("cuda")
+    out, ref = {}, None
+    for dtype in ("f64", "f32", "f16"):
+        sim = lbm.Lattice(19, n, scheme="aa", collision="bgk", omega=omega, geometry="periodic", dtype=dtype)
+        sim.init_equilibrium(None, u0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        _, u = sim.macroscopic()
+        info = sim.info()
+        sim.close()
+        # projection of u_x on the initial field: the mode's amplitude relative to t = 0
+        amp = float((u[0] * mode).sum() / (mode * mode).sum())
+        r = {"mlups": round(info.ntot / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+             "hbm_gbs": round(info.ntot * info.bytes_per_update / (ms * 1e-3) / 1e9, 1),
+             "mode_amplitude_ratio": amp}
+        if ref is None:
+            ref = u
+        else:
+            r["velocity_rel_l2_vs_f64"] = float(torch.linalg.vector_norm(u - ref) / torch.linalg.vector_norm(ref))
+        out[dtype] = r
+    k = 2 * math.pi / n
+    return {"workload": "D3Q19 BGK triply periodic Taylor-Green 256^3, u0=0.04, nu=0.01, AA-SoA",
+            "steps": steps, "analytic_exp_minus_3nuk2t": math.exp(-3 * W.TGV_NU * k * k * steps), **out}
+
+
+def run_ensemble(steps, seq_steps):
+    """512 independent D3Q19 TRT cavities (edge U{16..64}, Re U[100,1000],
+    u_lid 0.03), FP32-shifted AA: one launch per step replayed from a HIP
+    graph vs one launch per cavity per step."""
+    import torch
+    from paper_2010_11751_amd import lbm, workloads as W
+    members = W.ensemble(512)
+    cav = [lbm.Cavity(m.n, m.omega, m.u_lid) for m in members]
+    res = {}
+    for mode in ("graph", "sequential"):
+        b = lbm.Batch(cav, scheme="aa", collision="trt", dtype="f32", use_graph=(mode == "graph"),
+                      graph_steps=100, autotune=(mode == "graph"))
+        cells, fluid, blk = b.info()
+        n = steps if mode == "graph" else seq_steps
+        warm = 100 if mode == "graph" else 2
+        (b.step if mode == "graph" else b.step_sequential)(warm)
+        b.sync()
+        t0 = time.perf_counter()
+        (b.step if mode == "graph" else b.step_sequential)(n)
+        b.sync()
+        dt = time.perf_counter() - t0
+        masses, _ = b.invariants()
+        res[mode] = {"mlups": round(fluid * n / dt / 1e6, 1), "steps": n, "block_size": blk,
+                     "nonfinite_cavities": int(sum(1 for m in masses if m != m))}
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+    return {"workload": "512 D3Q19 TRT cavities, L~U{16..64}, Re~U[100,1000], u_lid=0.03, FP32-shifted AA",
+            "cells": int(cells), "fluid_cells": int(fluid), **res,
+            "speedup_graph_vs_sequential": round(res["graph"]["mlups"] / res["sequential"]["mlups"], 2)}
+
+
 def traffic_run(cav):
     import torch
     from paper_2010_11751_amd import lbm
@@ -159,6 +249,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-sweep", action="store_true", help="skip the nine FP64 scheme x collision runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 512^3 D3Q27, Taylor-Green and ensemble workloads")
     ap.add_argument("--traffic", action="store_true",
                     help="short run for hardware byte counters: one 1 GiB device copy, then 4 AA BGK steps of "
                          "the 256^3 cavity in FP64 and in FP32-shifted storage")
@@ -191,6 +283,14 @@ def main():
                 sweep.append({k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()
                               if k in ("scheme", "collision", "mlups", "algorithmic_gbs", "ms_per_step")})
                 print(f"# sweep {scheme} {coll}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    configs = {}
+    if not args.no_configs:
+        configs["cavity_512_d3q27_rr_f32"] = run_d3q27_rr(max(args.steps // 5, 20), 10)
+        print(f"# d3q27 rr 512: {configs['cavity_512_d3q27_rr_f32']['mlups']} MLUPS", file=sys.stderr, flush=True)
+        configs["taylor_green_256"] = run_taylor_green(2000)
+        print("# taylor-green done", file=sys.stderr, flush=True)
+        configs["ensemble_512"] = run_ensemble(1000, 100)
+        print(f"# ensemble: {configs['ensemble_512']['graph']['mlups']} MLUPS (graph)", file=sys.stderr, flush=True)
     copy_gbs = copy_ceiling_gbs()
     print(f"# copy kernel: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
 
@@ -232,6 +332,7 @@ def main():
                          "roofline": roofline(f32, "aa_bgk_f32_256")},
         "copy_kernel_gbs": round(copy_gbs, 1),
         "sweep_f64": sweep,
+        "configs": configs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

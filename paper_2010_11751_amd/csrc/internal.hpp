@@ -14,8 +14,13 @@ enum : uint8_t {
     FL_FLUID = 0,
     FL_WALL = 1,
     FL_LID = 2,
+    // Bits 2-4: wall plane of a fluid cell whose non-fluid neighbours are
+    // exactly the nine on one side (1 x-1, 2 x+1, 3 y-1, 4 y+1, 5 z-1,
+    // 6 z+1); such cells stay on the fast path.
+    FL_PLANE_SHIFT = 2,
+    FL_PLANE = 0x1C,
     FL_BORDER = 0x40,    // fluid cell on a box face: neighbours may wrap
-    FL_NEARWALL = 0x80,  // fluid cell with at least one non-fluid neighbour
+    FL_NEARWALL = 0x80,  // fluid cell with any other pattern of non-fluid neighbours
     FL_SLOW = FL_BORDER | FL_NEARWALL,
 };
 

@@ -169,6 +169,31 @@ __device__ __forceinline__ bool take_fast(uint8_t fl)
     return (fl & (FL_TYPE | FL_SLOW)) == FL_FLUID;
 }
 
+// Wall-plane cells stay on the fast path: their non-fluid neighbours are
+// exactly the nine on one side of the cell, the side with normal axis a and
+// sign s given by the plane code 1 + 2a + (s > 0). For a direction k the
+// neighbour x + c_k is then a wall iff c_k,a = s, and x - c_k iff c_k,a = -s.
+// The fast kernels apply those bounce-backs under a per-lane predicate;
+// waves without such lanes skip the branch.
+template <int Q, int K>
+__device__ __forceinline__ bool wall_to(uint8_t fl)  // x + c_k is a wall
+{
+    const int code = (fl & FL_PLANE) >> FL_PLANE_SHIFT;
+    bool w = false;
+    static_for<0, 3>([&](auto A) {
+        constexpr int a = A;
+        constexpr int c = L<Q>::c(K, a);
+        if constexpr (c != 0) w = w || code == 1 + 2 * a + (c > 0 ? 1 : 0);
+    });
+    return w;
+}
+
+template <int Q, int K>
+__device__ __forceinline__ bool wall_from(uint8_t fl)  // x - c_k is a wall
+{
+    return wall_to<Q, L<Q>::opp(K)>(fl);
+}
+
 // ---------------------------------------------------------------------------
 // Double-population scheme (Table 1, row 2Pop): collide pop(x), push
 // out_k(x + c_k) <- f_out_k, or out_kbar(x) <- f_out_k + pop_k(x + c_k) when
@@ -211,7 +236,12 @@ __device__ __forceinline__ void cell_2pop(const Field& F, const Relax<real_t<ST>
         if (!(fl & FL_SLOW)) {
             static_for<0, Q>([&](auto K) {
                 constexpr int k = K;
-                dst.raw_st_shift(i, k, offset<Q, k, 1>(F), typename ST::T(g[k]));
+                if (!wall_to<Q, k>(fl)) {
+                    dst.raw_st_shift(i, k, offset<Q, k, 1>(F), typename ST::T(g[k]));
+                } else {  // out_kbar(x) <- f_out_k + pop_k(x + c_k)
+                    const R w = R(src.raw_ld_shift(i, k, offset<Q, k, 1>(F)));
+                    dst.st(i, L<Q>::opp(k), g[k] + w);
+                }
             });
         } else if constexpr (PART == PART_ALL) {
             push_2pop_slow<Q, ST, LAYOUT>(F, i, fl, g);
@@ -295,8 +325,14 @@ __device__ __forceinline__ void cell_swap_stream(const Field& F, uint32_t i)
         if (!(fl & FL_SLOW)) {
             static_for<0, S::half>([&](auto K) {
                 constexpr int k = K;
-                a.raw_st(i, S::opp(k), theirs[k]);
-                a.raw_st_shift(i, k, offset<Q, k, 1>(F), mine[k]);
+                if (!wall_to<Q, k>(fl)) {
+                    a.raw_st(i, S::opp(k), theirs[k]);
+                    a.raw_st_shift(i, k, offset<Q, k, 1>(F), mine[k]);
+                } else {  // pop_kbar(x) += pop_k(x + c_k), the wall's term
+                    a.st(i, S::opp(k), real_t<ST>(mine[k]) + real_t<ST>(theirs[k]));
+                }
+                if (wall_from<Q, k>(fl))  // the wall's duty: pop_k(x) += pop_kbar(x - c_k)
+                    a.st(i, k, a.ld(i, k) + real_t<ST>(a.raw_ld_shift(i, S::opp(k), offset<Q, k, -1>(F))));
             });
         } else if constexpr (PART == PART_ALL) {
             swap_stream_slow<Q, ST, LAYOUT>(F, i, fl);
@@ -371,11 +407,22 @@ __device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<S
             else g[k] = a.ld_fast(i, S::opp(k), offset<Q, k, -1>(F), F.ntot);
         });
         issue_all(g);
+        if (fl & FL_PLANE) {  // pull across the wall plane: pop_k(x) + pop_kbar(x - c_k)
+            static_for<0, Q>([&](auto K) {
+                constexpr int k = K;
+                if (wall_from<Q, k>(fl)) g[k] += a.ld(i, k);
+            });
+        }
         collide<Q, MODEL, ST::shifted>(g, p);
         if (!take_fast<PART>(fl)) return;
         static_for<0, Q>([&](auto K) {
             constexpr int k = K;
-            a.raw_st_shift(i, k, offset<Q, k, 1>(F), typename ST::T(g[k]));
+            if (!wall_to<Q, k>(fl)) {
+                a.raw_st_shift(i, k, offset<Q, k, 1>(F), typename ST::T(g[k]));
+            } else {  // push across the wall plane: pop_kbar(x) <- f_out_k + pop_k(x + c_k)
+                const R w = R(a.raw_ld_shift(i, k, offset<Q, k, 1>(F)));
+                a.st(i, S::opp(k), g[k] + w);
+            }
         });
     }
 }
@@ -432,10 +479,10 @@ struct VecOf {
 template <int CPT>
 __device__ __forceinline__ bool group_fast(const uint8_t* flags, uint32_t i0)
 {
-    if constexpr (CPT == 2) return (*reinterpret_cast<const uint16_t*>(flags + i0) & 0xC3C3u) == 0;
-    else if constexpr (CPT == 4) return (*reinterpret_cast<const uint32_t*>(flags + i0) & 0xC3C3C3C3u) == 0;
-    else if constexpr (CPT == 8) return (*reinterpret_cast<const uint64_t*>(flags + i0) & 0xC3C3C3C3C3C3C3C3ull) == 0;
-    else return (flags[i0] & (FL_TYPE | FL_SLOW)) == FL_FLUID;
+    if constexpr (CPT == 2) return (*reinterpret_cast<const uint16_t*>(flags + i0) & 0xDFDFu) == 0;
+    else if constexpr (CPT == 4) return (*reinterpret_cast<const uint32_t*>(flags + i0) & 0xDFDFDFDFu) == 0;
+    else if constexpr (CPT == 8) return (*reinterpret_cast<const uint64_t*>(flags + i0) & 0xDFDFDFDFDFDFDFDFull) == 0;
+    else return (flags[i0] & (FL_TYPE | FL_SLOW | FL_PLANE)) == FL_FLUID;
 }
 
 template <int Q, int MODEL, class ST, int KIND, int CPT>

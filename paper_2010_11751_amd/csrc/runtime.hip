@@ -106,8 +106,10 @@ __global__ void k_flag_types(uint8_t* fl, int nx, int ny, int nz, int geometry)
     fl[i] = t;
 }
 
-// Fast-path hints: BORDER for fluid cells on a box face, NEARWALL for fluid
-// cells with a non-fluid cell among their 26 neighbours (wrapping).
+// Fast-path hints of a fluid cell, from its 26 neighbours (wrapping):
+// BORDER on a box face; a wall-plane code when the non-fluid neighbours are
+// exactly the nine on one side (the fast kernels bounce those back
+// themselves); NEARWALL for any other pattern of non-fluid neighbours.
 __global__ void k_flag_hints(uint8_t* fl, int nx, int ny, int nz)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -115,15 +117,28 @@ __global__ void k_flag_hints(uint8_t* fl, int nx, int ny, int nz)
     if (i >= n) return;
     if ((fl[i] & FL_TYPE) != FL_FLUID) return;
     const int z = (int)(i % nz), y = (int)((i / nz) % ny), x = (int)(i / ((uint64_t)ny * nz));
-    uint8_t h = 0;
-    if (x == 0 || x == nx - 1 || y == 0 || y == ny - 1 || z == 0 || z == nz - 1) h |= FL_BORDER;
+    const bool border = x == 0 || x == nx - 1 || y == 0 || y == ny - 1 || z == 0 || z == nz - 1;
+    int total = 0, side[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // solid neighbours at d_axis = -1 / +1
     for (int dx = -1; dx <= 1; ++dx)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dz = -1; dz <= 1; ++dz) {
                 const int xx = (x + dx + nx) % nx, yy = (y + dy + ny) % ny, zz = (z + dz + nz) % nz;
                 const uint64_t j = ((uint64_t)xx * ny + yy) * nz + zz;
-                if ((fl[j] & FL_TYPE) != FL_FLUID) h |= FL_NEARWALL;
+                if ((fl[j] & FL_TYPE) == FL_FLUID) continue;
+                ++total;
+                const int d[3] = {dx, dy, dz};
+                for (int a = 0; a < 3; ++a)
+                    if (d[a]) ++side[a][d[a] > 0];
             }
+    uint8_t h = 0;
+    if (border) {
+        h = FL_BORDER | (total ? FL_NEARWALL : 0);
+    } else if (total) {
+        h = FL_NEARWALL;
+        for (int a = 0; a < 3; ++a)
+            for (int sgn = 0; sgn < 2; ++sgn)
+                if (total == 9 && side[a][sgn] == 9) h = (uint8_t)((1 + 2 * a + sgn) << FL_PLANE_SHIFT);
+    }
     fl[i] |= h;
 }
 
@@ -170,11 +185,18 @@ __global__ void __launch_bounds__(256) k_reduce_pairs(const double* partial, int
 
 uint32_t grid_for(uint64_t n, int block) { return (uint32_t)((n + block - 1) / block); }
 
-// Streaming copy, 16 bytes per lane, grid-stride over 2048 blocks.
+// Streaming copy: one 16-byte vector per lane, one thread per vector, stores
+// nontemporal (the configuration that measured fastest on gfx950); a
+// grid-stride loop only beyond 2^31 vectors.
 __global__ void __launch_bounds__(256) k_copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, uint64_t n)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint4 v = src[i];
+        __builtin_nontemporal_store(v.x, &dst[i].x);
+        __builtin_nontemporal_store(v.y, &dst[i].y);
+        __builtin_nontemporal_store(v.z, &dst[i].z);
+        __builtin_nontemporal_store(v.w, &dst[i].w);
+    }
 }
 
 }  // namespace
@@ -521,8 +543,10 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
         for (int64_t g0 = 0; g0 < h->ntot; g0 += cpt) {
             // a group is fast when it is whole and every cell in it is a fast fluid cell
             bool fast = g0 + cpt <= h->ntot;
+            // the vector kernels have no wall-plane path, so those cells are listed too
+            const uint8_t off_path = cpt > 1 ? (FL_TYPE | FL_SLOW | FL_PLANE) : (FL_TYPE | FL_SLOW);
             for (int64_t i = g0; i < g0 + cpt && i < h->ntot; ++i)
-                fast = fast && (fl[i] & (FL_TYPE | FL_SLOW)) == FL_FLUID;
+                fast = fast && (fl[i] & off_path) == FL_FLUID;
             if (fast) continue;
             for (int64_t i = g0; i < g0 + cpt && i < h->ntot; ++i)
                 if ((fl[i] & FL_TYPE) == FL_FLUID) slow.push_back((uint32_t)i);
@@ -839,7 +863,7 @@ int lbm_device_copy(void* dst, const void* src, size_t bytes, void* stream)
         return fail(LBM_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
     if (bytes == 0) return LBM_OK;
     const uint64_t n = bytes / 16;
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_for(n, 256), 8192);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_for(n, 256), 1u << 23);
     k_copy16<<<grid, 256, 0, (hipStream_t)stream>>>((uint4*)dst, (const uint4*)src, n);
     HIP_TRY(hipGetLastError(), "copy launch");
     return LBM_OK;
