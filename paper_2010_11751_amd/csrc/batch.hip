@@ -60,15 +60,24 @@ __global__ void kb_flag_types(uint8_t* fl, int nx, int ny, int nz)
     fl[i] = inside ? FL_FLUID : (z == nz - 1 ? FL_LID : FL_WALL);
 }
 
-// Cavity fluid cells never sit on a box face; any fluid cell next to the
-// wall layer is flagged for the bounce-back path.
+// Fast-path hints of a cavity's fluid cells (they never sit on a box face):
+// the wall-plane code when the non-fluid neighbours are exactly the nine on
+// one side (the cell is one layer inside a single face), NEARWALL along the
+// edges and corners where two faces meet.
 __global__ void kb_flag_hints(uint8_t* fl, int nx, int ny, int nz)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t n = (uint32_t)nx * ny * nz;
     if (i >= n || (fl[i] & FL_TYPE) != FL_FLUID) return;
     const int z = (int)(i % nz), y = (int)((i / nz) % ny), x = (int)(i / ((uint32_t)ny * nz));
-    if (x == 1 || x == nx - 2 || y == 1 || y == ny - 2 || z == 1 || z == nz - 2) fl[i] |= FL_NEARWALL;
+    const int c[3] = {x, y, z}, hi[3] = {nx - 2, ny - 2, nz - 2};
+    int planes = 0, code = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (c[a] == 1) { ++planes; code = 1 + 2 * a; }
+        if (c[a] == hi[a]) { ++planes; code = 2 + 2 * a; }
+    }
+    if (planes == 1) fl[i] |= (uint8_t)(code << FL_PLANE_SHIFT);
+    else if (planes > 1) fl[i] |= FL_NEARWALL;
 }
 
 __global__ void kb_reduce_pairs(const double* partial, int nblocks, double* result)

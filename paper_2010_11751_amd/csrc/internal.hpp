@@ -35,7 +35,10 @@ enum Storage { STORE_F64 = 0, STORE_F32 = 1, STORE_F16 = 2 };
 #ifndef LBM_VEC_BYTES
 #define LBM_VEC_BYTES 0
 #endif
-constexpr int cells_per_thread(int elem_bytes) { return LBM_VEC_BYTES > 0 ? LBM_VEC_BYTES / elem_bytes : 1; }
+constexpr int cells_per_thread(int elem_bytes)
+{
+    return LBM_VEC_BYTES > elem_bytes ? LBM_VEC_BYTES / elem_bytes : 1;
+}
 
 struct StoreF64 {
     using T = double;
