@@ -24,8 +24,11 @@ LIB = os.path.join(HERE, "liblbm_oracle.so")
 FLUID, WALL, LID = 0, 1, 2
 CAVITY, PERIODIC, CHANNEL = 0, 1, 2
 BGK, TRT, REG, RR = 0, 1, 2, 3
+NW4, RM, HM, CM, CHM, K = 4, 5, 6, 7, 8, 9
 SOA, AOS = 0, 1
-MODELS = {"bgk": BGK, "trt": TRT, "reg": REG, "rr": RR}
+MODELS = {"bgk": BGK, "trt": TRT, "reg": REG, "rr": RR,
+          "nw4": NW4, "rm": RM, "hm": HM, "cm": CM, "chm": CHM, "k": K}
+MOMENT_SPACE = ("nw4", "rm", "hm", "cm", "chm", "k")
 
 
 def build(force: bool = True) -> str:
@@ -44,7 +47,8 @@ class _Cfg(ctypes.Structure):
                 ("nz", ctypes.c_int32), ("geometry", ctypes.c_int32), ("model", ctypes.c_int32),
                 ("layout", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("trt_lambda", ctypes.c_double),
-                ("omega_bulk", ctypes.c_double), ("u_lid", ctypes.c_double * 3),
+                ("omega_bulk", ctypes.c_double), ("omega3", ctypes.c_double),
+                ("omega4", ctypes.c_double), ("u_lid", ctypes.c_double * 3),
                 ("force", ctypes.c_double * 3)]
 
 
@@ -60,6 +64,8 @@ class Config:
     omega: float = 1.0
     trt_lambda: float = 0.25
     omega_bulk: float | None = None
+    omega3: float = 1.0
+    omega4: float = 1.0
     u_lid: tuple = (0.0, 0.0, 0.0)
     force: tuple = (0.0, 0.0, 0.0)
 
@@ -68,9 +74,12 @@ class Config:
         return self.nx * self.ny * self.nz
 
     def c_struct(self) -> _Cfg:
+        if self.model == K and self.q != 19:
+            raise ValueError("the cumulant model is defined on D3Q19 only")
         ob = self.omega if self.omega_bulk is None else self.omega_bulk
         return _Cfg(self.q, self.nx, self.ny, self.nz, self.geometry, self.model, self.layout, 0,
-                    self.omega, self.trt_lambda, ob, (ctypes.c_double * 3)(*self.u_lid),
+                    self.omega, self.trt_lambda, ob, self.omega3, self.omega4,
+                    (ctypes.c_double * 3)(*self.u_lid),
                     (ctypes.c_double * 3)(*self.force))
 
 

@@ -19,6 +19,12 @@
  *                               Taylor-Green decay, Couette, Poiseuille)
  *   REG ....................... pinned (stress relation, w=1 -> equilibrium,
  *                               bulk knob reduces to single relaxation)
+ *   moment-space models ....... pinned (relaxed moments of the output read
+ *   (NW4, RM, HM, CM, CHM, K)   back by direct sums, worked f_out_0 / f_out_10
+ *                               formula of Sec. 2.6, the identity of the
+ *                               linear families at equal rates, Maxwellian
+ *                               moments of the equilibrium, fixed point,
+ *                               Taylor-Green decay)
  *   RR ........................ equilibrium pinned (D3Q27 product form),
  *                               third/fourth-order recursion: parity unpinned
  *                               (the paper's RR formulas are in an absent
@@ -38,18 +44,21 @@
 
 enum { O_FLUID = 0, O_WALL = 1, O_LID = 2 };
 enum { O_CAVITY = 0, O_PERIODIC = 1, O_CHANNEL = 2 };
-enum { O_BGK = 0, O_TRT = 1, O_REG = 2, O_RR = 3 };
+enum { O_BGK = 0, O_TRT = 1, O_REG = 2, O_RR = 3,
+       O_NW4 = 4, O_RM = 5, O_HM = 6, O_CM = 7, O_CHM = 8, O_K = 9 };
 enum { O_SOA = 0, O_AOS = 1 };
 
 typedef struct {
     int32_t q, nx, ny, nz;
     int32_t geometry; /* O_CAVITY, O_PERIODIC, O_CHANNEL                       */
-    int32_t model;    /* O_BGK, O_TRT, O_REG, O_RR                             */
+    int32_t model;    /* O_BGK .. O_K                                          */
     int32_t layout;   /* O_SOA: pop[k][Ntot], O_AOS: pop[Ntot][Q]              */
     int32_t pad_;
     double omega;      /* shear relaxation frequency omega_nu                  */
     double trt_lambda; /* TRT "magic" parameter                                */
-    double omega_bulk; /* bulk relaxation frequency omega_nu_b (REG, RR)       */
+    double omega_bulk; /* bulk relaxation frequency omega_nu_b (REG, RR, MRT)  */
+    double omega3;     /* third-order moments of the moment-space models       */
+    double omega4;     /* fourth and higher orders of the moment-space models  */
     double u_lid[3];   /* velocity u_w of LID cells                            */
     double force[3];   /* test-only uniform body force; zero for the method    */
 } ocfg;
@@ -271,11 +280,14 @@ static void equilibrium_rr(const olat *L, double rho, const double u[3], double 
     }
 }
 
+static void equilibrium_nw4(const olat *L, double rho, const double u[3], double *E);
+
 void oracle_equilibrium(int q, int model, double rho, const double *u, double *E)
 {
     olat L;
     if (make_lattice(q, &L)) return;
     if (model == O_RR) equilibrium_rr(&L, rho, u, E);
+    else if (model >= O_NW4) equilibrium_nw4(&L, rho, u, E);
     else equilibrium2(&L, rho, u, E);
 }
 
@@ -332,6 +344,223 @@ static double a1_coefficient(const int n[3], const double u[3], double P[3][3])
     return s;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Moment-space collision models (Sec. 2.2, Sec. 2.6): BGK with the
+ * non-weighted fourth-order equilibrium (BGK-NW4), and the multi-relaxation-
+ * time models in raw (RM), Hermite (HM), central (CM) and central Hermite
+ * (CHM) moments and in cumulants (K), all in the non-weighted formulation:
+ * a set of Q populations corresponds one-to-one with its Q moments over the
+ * basis B of multi-indices n in {0,1,2}^3 whose monomial c^n does not vanish
+ * on every lattice velocity (D3Q19: at most two nonzero entries, 19 indices;
+ * D3Q27: all 27).
+ *
+ * Each moment family is a product over the axes of a polynomial p_{n_a}:
+ *   raw              1, c,     c^2
+ *   Hermite          1, c,     c^2 - c_s^2
+ *   central          1, c - u, (c - u)^2
+ *   central Hermite  1, c - u, (c - u)^2 - c_s^2
+ * and X_n = (1/rho) sum_k P_n(c_k) f_k (Eq. RM, with the 1/rho the worked
+ * f_out_0 example of Sec. 2.6 needs). The equilibria are the same moments of
+ * the continuous Maxwellian (density 1, mean u, variance c_s^2 per axis):
+ * raw 1, u, u^2 + c_s^2; Hermite 1, u, u^2; central 1, 0, c_s^2; central
+ * Hermite 1, 0, 0 (products over the axes).
+ *
+ * Relaxation (Eq. RMcoll): X*_n = X_n - w_n (X_n - X^eq_n), with w = omega_nu
+ * for the off-diagonal second-order moments, the mixing of Eq. bulk for the
+ * diagonal ones, omega_3 at third order and omega_4 at orders four and up.
+ * The cumulant model replaces the fourth-order central moments by the
+ * cumulants C_220 = k_220 - k_200 k_020 - 2 k_110^2 (and permutations) and
+ * relaxes those. The outgoing populations are the solution of
+ * sum_k P_n(c_k) f_out_k = rho X*_n for every n in B. */
+
+enum { FAM_RAW = 0, FAM_HERMITE = 1, FAM_CENTRAL = 2, FAM_CHERMITE = 3 };
+
+static int moment_basis(int q, int nb[27][3])
+{
+    int a, b, e, n = 0;
+    for (a = 0; a <= 2; ++a)
+        for (b = 0; b <= 2; ++b)
+            for (e = 0; e <= 2; ++e) {
+                if (q == 19 && a > 0 && b > 0 && e > 0) continue;
+                nb[n][0] = a;
+                nb[n][1] = b;
+                nb[n][2] = e;
+                ++n;
+            }
+    return n;
+}
+
+static double axis_poly(int fam, int n, double c, double u)
+{
+    double x = (fam == FAM_CENTRAL || fam == FAM_CHERMITE) ? c - u : c;
+    if (n == 0) return 1.0;
+    if (n == 1) return x;
+    return (fam == FAM_HERMITE || fam == FAM_CHERMITE) ? x * x - 1.0 / 3.0 : x * x;
+}
+
+static double axis_maxwellian(int fam, int n, double u)
+{
+    if (n == 0) return 1.0;
+    switch (fam) {
+    case FAM_RAW: return n == 1 ? u : u * u + 1.0 / 3.0;
+    case FAM_HERMITE: return n == 1 ? u : u * u;
+    case FAM_CENTRAL: return n == 1 ? 0.0 : 1.0 / 3.0;
+    default: return 0.0;
+    }
+}
+
+/* T[n][k] = P_n(c_k) of a family at velocity u. */
+static void moment_matrix(const olat *L, int fam, const double u[3], int nb[27][3], int nm,
+                          double T[27][27])
+{
+    int n, k, a;
+    for (n = 0; n < nm; ++n)
+        for (k = 0; k < L->q; ++k) {
+            double v = 1.0;
+            for (a = 0; a < 3; ++a) v *= axis_poly(fam, nb[n][a], L->c[k][a], u[a]);
+            T[n][k] = v;
+        }
+}
+
+/* Solve T x = b (m x m) by Gauss-Jordan elimination with partial pivoting. */
+static void solve(int m, double T[27][27], const double *b, double *x)
+{
+    double A[27][28];
+    int r, c, p;
+    for (r = 0; r < m; ++r) {
+        for (c = 0; c < m; ++c) A[r][c] = T[r][c];
+        A[r][m] = b[r];
+    }
+    for (c = 0; c < m; ++c) {
+        int piv = c;
+        for (r = c + 1; r < m; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (piv != c)
+            for (p = 0; p <= m; ++p) { double t = A[c][p]; A[c][p] = A[piv][p]; A[piv][p] = t; }
+        for (r = 0; r < m; ++r) {
+            double fct;
+            if (r == c) continue;
+            fct = A[r][c] / A[c][c];
+            for (p = c; p <= m; ++p) A[r][p] -= fct * A[c][p];
+        }
+    }
+    for (r = 0; r < m; ++r) x[r] = A[r][m] / A[r][r];
+}
+
+/* X*_n from X_n and X^eq_n for the orders and rates described above. */
+static void relax_moments(const ocfg *g, int nb[27][3], int nm, const double *X, const double *Xeq,
+                          double *Xs)
+{
+    double wm = (g->omega_bulk - g->omega) / 3.0, wp = wm + g->omega;
+    int n, m, a;
+    for (n = 0; n < nm; ++n) {
+        int ord = nb[n][0] + nb[n][1] + nb[n][2];
+        int diag = -1;
+        for (a = 0; a < 3; ++a)
+            if (nb[n][a] == 2 && ord == 2) diag = a;
+        if (ord <= 1) {
+            Xs[n] = X[n];
+        } else if (diag >= 0) {
+            /* Eq. bulk: X*_aa = X_aa - w+ (X_aa - eq) - w- sum_{b != a} (X_bb - eq) */
+            Xs[n] = X[n] - wp * (X[n] - Xeq[n]);
+            for (m = 0; m < nm; ++m) {
+                int om = nb[m][0] + nb[m][1] + nb[m][2];
+                if (m != n && om == 2 && (nb[m][0] == 2 || nb[m][1] == 2 || nb[m][2] == 2))
+                    Xs[n] -= wm * (X[m] - Xeq[m]);
+            }
+        } else if (ord == 2) {
+            Xs[n] = X[n] - g->omega * (X[n] - Xeq[n]);
+        } else if (ord == 3) {
+            Xs[n] = X[n] - g->omega3 * (X[n] - Xeq[n]);
+        } else {
+            Xs[n] = X[n] - g->omega4 * (X[n] - Xeq[n]);
+        }
+    }
+}
+
+static int find_index(int nb[27][3], int nm, int a, int b, int e)
+{
+    int n;
+    for (n = 0; n < nm; ++n)
+        if (nb[n][0] == a && nb[n][1] == b && nb[n][2] == e) return n;
+    return -1;
+}
+
+/* BGK-NW4 equilibrium: the populations whose raw moments over B are the
+ * Maxwellian ones. */
+static void equilibrium_nw4(const olat *L, double rho, const double u[3], double *E)
+{
+    int nb[27][3], nm = moment_basis(L->q, nb), n, a;
+    double T[27][27], Meq[27];
+    double zero[3] = {0.0, 0.0, 0.0};
+    moment_matrix(L, FAM_RAW, zero, nb, nm, T);
+    for (n = 0; n < nm; ++n) {
+        double v = rho;
+        for (a = 0; a < 3; ++a) v *= axis_maxwellian(FAM_RAW, nb[n][a], u[a]);
+        Meq[n] = v;
+    }
+    solve(nm, T, Meq, E);
+}
+
+static void collide_moment_space(const olat *L, const ocfg *g, double rho, const double u[3],
+                                 const double *f, double *fout)
+{
+    int nb[27][3], nm = moment_basis(L->q, nb), n, k, a;
+    double T[27][27], X[27], Xeq[27], Xs[27], b[27];
+    int fam = g->model == O_HM ? FAM_HERMITE : g->model == O_CHM ? FAM_CHERMITE
+            : (g->model == O_CM || g->model == O_K) ? FAM_CENTRAL : FAM_RAW;
+
+    if (g->model == O_NW4) {
+        double E[27];
+        equilibrium_nw4(L, rho, u, E);
+        for (k = 0; k < L->q; ++k) fout[k] = f[k] - g->omega * (f[k] - E[k]);
+        return;
+    }
+    if (g->model == O_K && L->q != 19) {
+        for (k = 0; k < L->q; ++k) fout[k] = NAN;
+        return;
+    }
+    moment_matrix(L, fam, u, nb, nm, T);
+    for (n = 0; n < nm; ++n) {
+        double s = 0.0, e = 1.0;
+        for (k = 0; k < L->q; ++k) s += T[n][k] * f[k];
+        X[n] = s / rho;
+        for (a = 0; a < 3; ++a) e *= axis_maxwellian(fam, nb[n][a], u[a]);
+        Xeq[n] = e;
+    }
+    if (g->model == O_K) {
+        /* Orders two and three: cumulants equal central moments. Order four
+         * (D3Q19: 220, 202, 022): relax C = k_aabb - k_aa k_bb - 2 k_ab^2
+         * towards 0 and rebuild k*_aabb from C* and the relaxed second order. */
+        int p, axes[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+        double Xtmp[27];
+        ocfg g2 = *g;
+        g2.omega4 = 0.0; /* fourth order handled below */
+        relax_moments(&g2, nb, nm, X, Xeq, Xtmp);
+        for (n = 0; n < nm; ++n) Xs[n] = Xtmp[n];
+        for (p = 0; p < 3; ++p) {
+            int d[3] = {0, 0, 0}, e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0}, o[3] = {0, 0, 0};
+            int i4, i1, i2, io;
+            double C, Cs;
+            d[axes[p][0]] = 2; d[axes[p][1]] = 2;
+            e1[axes[p][0]] = 2;
+            e2[axes[p][1]] = 2;
+            o[axes[p][0]] = 1; o[axes[p][1]] = 1;
+            i4 = find_index(nb, nm, d[0], d[1], d[2]);
+            i1 = find_index(nb, nm, e1[0], e1[1], e1[2]);
+            i2 = find_index(nb, nm, e2[0], e2[1], e2[2]);
+            io = find_index(nb, nm, o[0], o[1], o[2]);
+            C = X[i4] - X[i1] * X[i2] - 2.0 * X[io] * X[io];
+            Cs = (1.0 - g->omega4) * C;
+            Xs[i4] = Cs + Xs[i1] * Xs[i2] + 2.0 * Xs[io] * Xs[io];
+        }
+    } else {
+        relax_moments(g, nb, nm, X, Xeq, Xs);
+    }
+    for (n = 0; n < nm; ++n) b[n] = rho * Xs[n];
+    solve(nm, T, b, fout);
+}
+
 static void collide(const olat *L, const ocfg *g, const double *f, double *fout)
 {
     int k, a, b;
@@ -362,6 +591,8 @@ static void collide(const olat *L, const ocfg *g, const double *f, double *fout)
                     s += (L->c[k][a] * L->c[k][b] - (a == b ? 1.0 / 3.0 : 0.0)) * P[a][b];
             fout[k] = E[k] + L->t[k] * 4.5 * s;
         }
+    } else if (g->model >= O_NW4) {
+        collide_moment_space(L, g, rho, u, f, fout);
     } else { /* O_RR */
         double P[3][3];
         int n[3];
@@ -401,7 +632,7 @@ int oracle_collide(const ocfg *g, const double *f, double *fout)
 /* State set-up: wall cells hold their momentum-exchange terms in every slot
  * (Eq. storage2), fluid cells hold E(rho, u) (Eq. storage1). rho and u may be
  * NULL (rho = 1, u = 0); u is given as u[3][Ntot]. The equilibrium is the
- * model's own (E^S for RR). */
+ * model's own (E^S for RR, the NW4 equilibrium for the moment-space models). */
 int oracle_init_state(const ocfg *g, const uint8_t *flags, const double *rho,
                       const double *u, double *pop)
 {
@@ -416,6 +647,7 @@ int oracle_init_state(const ocfg *g, const uint8_t *flags, const double *rho,
             double r = rho ? rho[i] : 1.0, v[3] = {0.0, 0.0, 0.0}, E[27];
             if (u) { v[0] = u[i]; v[1] = u[n + i]; v[2] = u[2 * n + i]; }
             if (g->model == O_RR) equilibrium_rr(&L, r, v, E);
+            else if (g->model >= O_NW4) equilibrium_nw4(&L, r, v, E);
             else equilibrium2(&L, r, v, E);
             for (k = 0; k < L.q; ++k) pop[at(g, i, k)] = E[k];
         }
