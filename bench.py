@@ -201,6 +201,56 @@ def run_ensemble(steps, seq_steps):
             "speedup_graph_vs_sequential": round(res["graph"]["mlups"] / res["sequential"]["mlups"], 2)}
 
 
+COLLISION_MODELS = ("bgk", "trt", "reg", "rr", "nw4", "rm", "hm", "cm", "chm", "k")
+
+
+def run_collision_models(steps, warmup, cav):
+    """The ten collision models (BGK-W2, TRT, REG, RR, BGK-NW4, RM, HM, CM,
+    CHM, cumulant; high-order rates 1) on the 256^3 cavity, AA-SoA, in FP64
+    and FP32-shifted storage; the paper finds the slowest within 2x of the
+    fastest (Sec. 3.2.3)."""
+    out = {}
+    for dtype in ("f64", "f32"):
+        rows = []
+        for coll in COLLISION_MODELS:
+            r = run_case("aa", coll, dtype, steps, warmup, cav)
+            rows.append({"collision": coll, "mlups": round(r["mlups"], 1),
+                         "algorithmic_gbs": round(r["algorithmic_gbs"], 1), "block_size": r["block_size"],
+                         "finite": r["finite"]})
+            print(f"# model {coll} {dtype}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        m = [r["mlups"] for r in rows]
+        out[dtype] = {"runs": rows, "slowest_over_fastest": round(min(m) / max(m), 3)}
+    return out
+
+
+DOMAIN_SIZES = (16, 24, 32, 48, 64, 96, 128, 192, 256, 320, 400)
+
+
+def domain_sweep():
+    """MLUPS against cavity size N (walls included) for AA vs 2Pop and BGK vs
+    RR, FP64 D3Q19 SoA, as in the domain-size study of Sec. 3.2.4; steps per
+    size chosen for about 0.3 s of timed work."""
+    from paper_2010_11751_amd import lbm, workloads as W
+    rows = []
+    for n in DOMAIN_SIZES:
+        omega = W.omega_from_nu(0.05 * n / 1000.0)
+        for scheme in ("aa", "2pop"):
+            for coll in ("bgk", "rr"):
+                fluid = (n - 2) ** 3
+                steps = int(min(2000, max(20, 0.3 / (fluid / 15e9))))
+                steps += steps % 2
+                sim = lbm.Lattice(19, n, scheme=scheme, collision=coll, omega=omega, u_lid=0.05)
+                ms, _ = time_steps(sim, steps, max(steps // 10, 10))
+                info = sim.info()
+                sim.close()
+                r = {"n": n, "scheme": scheme, "collision": coll, "steps": steps,
+                     "ms_per_step": round(ms, 5), "mlups": round(info.fluid_cells / (ms * 1e-3) / 1e6, 1),
+                     "algorithmic_gbs": round(info.fluid_cells * info.bytes_per_update / (ms * 1e-3) / 1e9, 1)}
+                rows.append(r)
+                print(f"# N={n} {scheme} {coll}: {r['mlups']} MLUPS", file=sys.stderr, flush=True)
+    print(json.dumps({"domain_sweep": rows, "dtype": "f64", "lattice": "D3Q19", "layout": "SoA"}), flush=True)
+
+
 def traffic_run(cav):
     import torch
     from paper_2010_11751_amd import lbm
@@ -247,10 +297,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--no-sweep", action="store_true", help="skip the nine FP64 scheme x collision runs")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the nine FP64 scheme x collision runs and the ten-model sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 512^3 D3Q27, Taylor-Green and ensemble workloads")
+    ap.add_argument("--domain-sweep", action="store_true",
+                    help="only the MLUPS-vs-cavity-size sweep (N = 16..400; AA vs 2Pop, BGK vs RR, FP64)")
     ap.add_argument("--traffic", action="store_true",
                     help="short run for hardware byte counters: one 1 GiB device copy, then 4 AA BGK steps of "
                          "the 256^3 cavity in FP64 and in FP32-shifted storage")
@@ -270,6 +322,9 @@ def main():
     if args.traffic:
         traffic_run(cav)
         return
+    if args.domain_sweep:
+        domain_sweep()
+        return
 
     head = run_case("aa", "bgk", "f64", args.steps, args.warmup, cav)
     print(f"# f64 aa bgk: {head['mlups']:.0f} MLUPS, {head['algorithmic_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
@@ -283,6 +338,9 @@ def main():
                 sweep.append({k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()
                               if k in ("scheme", "collision", "mlups", "algorithmic_gbs", "ms_per_step")})
                 print(f"# sweep {scheme} {coll}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    models = None
+    if not args.no_sweep:
+        models = run_collision_models(max(args.steps // 5, 20), max(args.warmup // 5, 10), cav)
     configs = {}
     if not args.no_configs:
         configs["cavity_512_d3q27_rr_f32"] = run_d3q27_rr(max(args.steps // 5, 20), 10)
@@ -332,6 +390,7 @@ def main():
                          "roofline": roofline(f32, "aa_bgk_f32_256")},
         "copy_kernel_gbs": round(copy_gbs, 1),
         "sweep_f64": sweep,
+        "collision_models": models,
         "configs": configs,
         "cpu_baseline": cpu,
     }

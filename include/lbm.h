@@ -12,8 +12,11 @@
  *     wall cells storing the precomputed term        (Eqs. storage1, storage2)
  *   - memory-access schemes 2Pop / swap / AA        (Sec. 2.3, Table 1)
  *   - layouts SoA pop[k][N] and AoS pop[N][Q]       (Sec. 2.3)
- *   - collision models BGK, TRT, regularized, recursive regularized (Sec. 2.2),
- *     with the bulk-viscosity knob of Sec. 2.6 (Eq. bulk).
+ *   - collision models BGK, TRT, regularized, recursive regularized, and the
+ *     moment-space models of Sec. 2.2 (BGK with the non-weighted fourth-order
+ *     equilibrium; multi-relaxation-time in raw, Hermite, central, central
+ *     Hermite moments and cumulants, Sec. 2.6 Eq. RMcoll), with the
+ *     bulk-viscosity knob of Sec. 2.6 (Eq. bulk).
  * The handle plays the role of the paper's stateless per-cell operator over
  * a lattice pointer, velocities, weights, omega and dimensions (Sec. 2.5).
  *
@@ -57,7 +60,22 @@ enum lbm_status {
     LBM_EUNSUPPORTED = -5  /* valid but unsupported combination               */
 };
 enum lbm_scheme { LBM_2POP = 0, LBM_SWAP = 1, LBM_AA = 2 };
-enum lbm_collision { LBM_BGK = 0, LBM_TRT = 1, LBM_REG = 2, LBM_RR = 3 };
+/* BGK: BGK with the weighted second-order equilibrium (BGK-W2). TRT: two
+ * relaxation times (Lambda). REG / RR: regularized and recursive regularized
+ * (weighted Hermite). The moment-space models use the non-weighted basis of
+ * Q moments (multi-indices in {0,1,2}^3; D3Q19 drops those with three nonzero
+ * entries) and relax X*_n = X_n - w_n (X_n - X^eq_n) (Sec. 2.6, Eq. RMcoll):
+ *   LBM_BGK_NW4  BGK with the non-weighted fourth-order equilibrium
+ *   LBM_RM       raw moments          LBM_HM   Hermite moments
+ *   LBM_CM       central moments      LBM_CHM  central Hermite moments
+ *   LBM_K        cumulants (D3Q19 only; fourth-order cumulants relax)
+ * with w = omega (second order, trace at omega_bulk per Eq. bulk), omega3
+ * (third order) and omega4 (fourth order and up). All of them start from
+ * and keep the NW4 equilibrium as their fixed point. */
+enum lbm_collision {
+    LBM_BGK = 0, LBM_TRT = 1, LBM_REG = 2, LBM_RR = 3,
+    LBM_BGK_NW4 = 4, LBM_RM = 5, LBM_HM = 6, LBM_CM = 7, LBM_CHM = 8, LBM_K = 9
+};
 enum lbm_dtype { LBM_F64 = 0, LBM_F32_SHIFTED = 1, LBM_F16_SHIFTED = 2 };
 enum lbm_layout { LBM_SOA = 0, LBM_AOS = 1 };
 enum lbm_geometry { LBM_CAVITY = 0, LBM_PERIODIC = 1, LBM_CHANNEL = 2 };
@@ -81,7 +99,12 @@ typedef struct lbm_desc {
     int block_size;       /* threads per block of the step kernels; 0 = auto   */
     double omega;         /* shear relaxation frequency, 0 < omega < 2         */
     double trt_lambda;    /* TRT magic parameter (default 1/4)                 */
-    double omega_bulk;    /* bulk relaxation of REG/RR; <= 0 means = omega     */
+    double omega_bulk;    /* bulk relaxation of REG/RR/moment-space models;
+                             <= 0 means = omega                                */
+    double omega3;        /* moment-space models: rate of the third-order
+                             moments; <= 0 means 1 (equilibrate)               */
+    double omega4;        /* moment-space models: rate of the fourth- and
+                             higher-order moments; <= 0 means 1                */
     double lid_velocity[3]; /* u_w of LID cells, |u_w| < 0.4                   */
     void *stream;         /* hipStream_t; NULL = the null stream               */
     void *pop;            /* optional caller-owned device buffers (see         */
@@ -204,7 +227,8 @@ typedef struct lbm_batch_opts {
 } lbm_batch_opts;
 
 /* Create count cavities (FP64 or shifted FP32/FP16, D3Q19, any scheme but
- * swap, any collision). opts may be NULL. Initial state: rho = 1, u = 0. */
+ * swap, any collision; omega_bulk = omega and, for the moment-space models,
+ * omega3 = omega4 = 1). opts may be NULL. Initial state: rho = 1, u = 0. */
 lbm_batch *lbm_batch_create(int count, const lbm_cavity_desc *d, int scheme, int collision,
                             int storage_dtype, const lbm_batch_opts *opts);
 int lbm_batch_step(lbm_batch *b, int n);

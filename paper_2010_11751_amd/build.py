@@ -22,6 +22,8 @@ SOURCES = [
     "runtime.hip", "batch.hip",
     "k_q19_f64.hip", "k_q19_f32.hip", "k_q19_f16.hip",
     "k_q27_f64.hip", "k_q27_f32.hip", "k_q27_f16.hip",
+    "k_q19_f64_mrt.hip", "k_q19_f32_mrt.hip", "k_q19_f16_mrt.hip",
+    "k_q27_f64_mrt.hip", "k_q27_f32_mrt.hip", "k_q27_f16_mrt.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -210,6 +210,7 @@ int autotune_batch(lbm_batch* b)
     float best = 1e30f;
     int best_b = 256;
     for (int c : cand) {
+        if (c > max_step_block(19, b->collision, 8)) continue;
         int rc = build_tiles(b, c);
         for (int s = 0; !rc && s < 2; ++s) rc = launch_batch_step(b);
         if (rc) return rc;
@@ -260,7 +261,7 @@ lbm_batch* lbm_batch_create(int count, const lbm_cavity_desc* d, int scheme, int
         fail(scheme == LBM_SWAP ? LBM_EUNSUPPORTED : LBM_EINVAL, "batch schemes: 2Pop or AA");
         return nullptr;
     }
-    if (collision < LBM_BGK || collision > LBM_RR || storage_dtype < LBM_F64 || storage_dtype > LBM_F16_SHIFTED) {
+    if (collision < LBM_BGK || collision > LBM_K || storage_dtype < LBM_F64 || storage_dtype > LBM_F16_SHIFTED) {
         fail(LBM_EINVAL, "unknown collision model or storage dtype");
         return nullptr;
     }
@@ -329,6 +330,8 @@ lbm_batch* lbm_batch_create(int count, const lbm_cavity_desc* d, int scheme, int
         const double lam = d[c].trt_lambda > 0.0 ? d[c].trt_lambda : 0.25;
         r.omega_m = collision == LBM_TRT ? 1.0 / (0.5 + lam / (1.0 / d[c].omega - 0.5)) : d[c].omega;
         r.omega_b = d[c].omega;
+        r.omega3 = 1.0;
+        r.omega4 = 1.0;
         b->cav[0][c] = BatchCavity{F, r};
     }
     hipError_t e = hipMalloc(&b->pool, total);
@@ -369,7 +372,7 @@ lbm_batch* lbm_batch_create(int count, const lbm_cavity_desc* d, int scheme, int
         fail(LBM_EINVAL, "block_size must be a multiple of 64 up to 1024");
         return bail(0);
     }
-    if (build_tiles(b, block)) return bail(0);
+    if (build_tiles(b, std::min(block, max_step_block(19, b->collision, 8)))) return bail(0);
     if (b->opts.autotune && (autotune_batch(b) || init_batch_state(b))) return bail(0);
     e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {

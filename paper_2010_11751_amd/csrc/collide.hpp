@@ -10,16 +10,19 @@
 #pragma once
 
 #include "lattice.hpp"
+#include "moments.hpp"
 
 namespace lbm {
 
-enum Model { BGK = 0, TRT = 1, REG = 2, RR = 3 };
+enum Model { BGK = 0, TRT = 1, REG = 2, RR = 3, NW4 = 4, RM = 5, HM = 6, CM = 7, CHM = 8, CUM = 9 };
 
 template <class R>
 struct Relax {
     R omega;    // shear relaxation omega_nu (TRT: omega_plus)
     R omega_m;  // TRT antisymmetric rate omega_minus
-    R omega_b;  // bulk relaxation omega_nu_b (REG, RR)
+    R omega_b;  // bulk relaxation omega_nu_b (REG, RR, moment-space models)
+    R omega3;   // third-order moments (moment-space models)
+    R omega4;   // fourth and higher orders (moment-space models)
 };
 
 template <int Q, class R>
@@ -214,7 +217,19 @@ __device__ __forceinline__ void collide(R (&g)[Q], const Relax<R>& p)
     CellMoments<Q, R> m;
     cell_moments<Q, SHIFT>(g, m);
 
-    if constexpr (MODEL == BGK || MODEL == TRT) {
+    if constexpr (MODEL >= NW4) {
+        constexpr int FAM = (MODEL == NW4 || MODEL == RM) ? FAM_RAW
+                          : MODEL == HM ? FAM_HERMITE : MODEL == CHM ? FAM_CHERMITE : FAM_CENTRAL;
+        MomentRates<R> r;
+        if constexpr (MODEL == NW4) {
+            // BGK with the NW4 equilibrium: every moment relaxes at omega.
+            r = MomentRates<R>{p.omega, p.omega, R(0), p.omega, p.omega};
+        } else {
+            const R wm = (p.omega_b - p.omega) * R(1.0 / 3.0);
+            r = MomentRates<R>{p.omega, wm + p.omega, wm, p.omega3, p.omega4};
+        }
+        collide_moment_space<Q, FAM, MODEL == CUM>(g, m.s, m.d, m.base, m.rho, m.u, r);
+    } else if constexpr (MODEL == BGK || MODEL == TRT) {
         Eq2<Q, R> e;
         equilibrium2<Q>(m.base, m.rho, m.j, m.u, e);
         const R w = p.omega;
@@ -281,14 +296,17 @@ __device__ __forceinline__ void collide(R (&g)[Q], const Relax<R>& p)
 }
 
 // Equilibrium of the model at (rho, u) in the storage representation
-// (E^S of the support set for RR, BGK-W2 otherwise).
+// (E^S of the support set for RR, the NW4 equilibrium for the moment-space
+// models, BGK-W2 otherwise).
 template <int Q, int MODEL, bool SHIFT, class R>
 __device__ __forceinline__ void equilibrium(R rho, const R (&u)[3], R (&g)[Q])
 {
     using S = L<Q>;
     const R base = SHIFT ? rho - R(1) : rho;
     const R j[3] = {rho * u[0], rho * u[1], rho * u[2]};
-    if constexpr (MODEL == RR) {
+    if constexpr (MODEL >= NW4) {
+        equilibrium_nw4<Q>(base, rho, u, g);
+    } else if constexpr (MODEL == RR) {
         using H = HS<Q, true>;
         R P[3][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
         R A[H::size];

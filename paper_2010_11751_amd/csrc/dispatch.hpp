@@ -97,8 +97,10 @@ hipError_t launch_model(const Launch& L, hipStream_t s)
     return hipGetLastError();
 }
 
+using LaunchFnPtr = hipError_t (*)(const Launch&, hipStream_t);
+
 template <int Q, class ST, int LAYOUT>
-hipError_t launch_layout(const Launch& L, hipStream_t s)
+hipError_t launch_layout(const Launch& L, hipStream_t s, LaunchFnPtr moment_space)
 {
     const dim3 g(L.grid), b(L.block);
     switch (L.op) {
@@ -114,17 +116,44 @@ hipError_t launch_layout(const Launch& L, hipStream_t s)
         case TRT: return launch_model<Q, ST, LAYOUT, TRT>(L, s);
         case REG: return launch_model<Q, ST, LAYOUT, REG>(L, s);
         case RR: return launch_model<Q, ST, LAYOUT, RR>(L, s);
+        case NW4: case RM: case HM: case CM: case CHM: case CUM: return moment_space(L, s);
         default: return hipErrorInvalidValue;
         }
     }
     return hipGetLastError();
 }
 
-template <int Q, class ST>
-hipError_t launch_tu(const Launch& L, hipStream_t s)
+// Model launches of the moment-space models, kept in translation units of
+// their own (they are the largest kernels to compile).
+template <int Q, class ST, int LAYOUT>
+hipError_t launch_layout_moment_space(const Launch& L, hipStream_t s)
 {
-    if (L.layout == LAYOUT_SOA) return launch_layout<Q, ST, LAYOUT_SOA>(L, s);
-    if (L.layout == LAYOUT_AOS) return launch_layout<Q, ST, LAYOUT_AOS>(L, s);
+    switch (L.model) {
+    case NW4: return launch_model<Q, ST, LAYOUT, NW4>(L, s);
+    case RM: return launch_model<Q, ST, LAYOUT, RM>(L, s);
+    case HM: return launch_model<Q, ST, LAYOUT, HM>(L, s);
+    case CM: return launch_model<Q, ST, LAYOUT, CM>(L, s);
+    case CHM: return launch_model<Q, ST, LAYOUT, CHM>(L, s);
+    case CUM:
+        if constexpr (Q == 19) return launch_model<Q, ST, LAYOUT, CUM>(L, s);
+        else return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int Q, class ST>
+hipError_t launch_tu(const Launch& L, hipStream_t s, LaunchFnPtr moment_space)
+{
+    if (L.layout == LAYOUT_SOA) return launch_layout<Q, ST, LAYOUT_SOA>(L, s, moment_space);
+    if (L.layout == LAYOUT_AOS) return launch_layout<Q, ST, LAYOUT_AOS>(L, s, moment_space);
+    return hipErrorInvalidValue;
+}
+
+template <int Q, class ST>
+hipError_t launch_tu_moment_space(const Launch& L, hipStream_t s)
+{
+    if (L.layout == LAYOUT_SOA) return launch_layout_moment_space<Q, ST, LAYOUT_SOA>(L, s);
+    if (L.layout == LAYOUT_AOS) return launch_layout_moment_space<Q, ST, LAYOUT_AOS>(L, s);
     return hipErrorInvalidValue;
 }
 

@@ -66,8 +66,16 @@ struct Field {
     int nx, ny, nz;
 };
 
+// Largest block of the step kernels: the moment-space models (model >= 4)
+// and D3Q27 in FP64 need more registers per lane than 1024-thread blocks
+// leave them (128 VGPRs).
+constexpr int max_step_block(int q, int model, int elem_bytes)
+{
+    return (model >= 4 || (q == 27 && elem_bytes == 8)) ? 256 : 1024;
+}
+
 struct RelaxD {
-    double omega, omega_m, omega_b;
+    double omega, omega_m, omega_b, omega3, omega4;
 };
 
 struct InitArgs {
@@ -113,5 +121,12 @@ hipError_t launch_q19_f16(const Launch& L, hipStream_t s);
 hipError_t launch_q27_f64(const Launch& L, hipStream_t s);
 hipError_t launch_q27_f32(const Launch& L, hipStream_t s);
 hipError_t launch_q27_f16(const Launch& L, hipStream_t s);
+// Moment-space models (model >= NW4): step, init and batch launches.
+hipError_t launch_q19_f64_mrt(const Launch& L, hipStream_t s);
+hipError_t launch_q19_f32_mrt(const Launch& L, hipStream_t s);
+hipError_t launch_q19_f16_mrt(const Launch& L, hipStream_t s);
+hipError_t launch_q27_f64_mrt(const Launch& L, hipStream_t s);
+hipError_t launch_q27_f32_mrt(const Launch& L, hipStream_t s);
+hipError_t launch_q27_f16_mrt(const Launch& L, hipStream_t s);
 
 }  // namespace lbm

@@ -2,5 +2,5 @@
 #include "dispatch.hpp"
 
 namespace lbm {
-hipError_t launch_q19_f16(const Launch& L, hipStream_t s) { return launch_tu<19, StoreF16>(L, s); }
+hipError_t launch_q19_f16(const Launch& L, hipStream_t s) { return launch_tu<19, StoreF16>(L, s, launch_q19_f16_mrt); }
 }  // namespace lbm

@@ -2,5 +2,5 @@
 #include "dispatch.hpp"
 
 namespace lbm {
-hipError_t launch_q19_f64(const Launch& L, hipStream_t s) { return launch_tu<19, StoreF64>(L, s); }
+hipError_t launch_q19_f64(const Launch& L, hipStream_t s) { return launch_tu<19, StoreF64>(L, s, launch_q19_f64_mrt); }
 }  // namespace lbm

@@ -2,5 +2,5 @@
 #include "dispatch.hpp"
 
 namespace lbm {
-hipError_t launch_q27_f16(const Launch& L, hipStream_t s) { return launch_tu<27, StoreF16>(L, s); }
+hipError_t launch_q27_f16(const Launch& L, hipStream_t s) { return launch_tu<27, StoreF16>(L, s, launch_q27_f16_mrt); }
 }  // namespace lbm

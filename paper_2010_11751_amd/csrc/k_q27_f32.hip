@@ -2,5 +2,5 @@
 #include "dispatch.hpp"
 
 namespace lbm {
-hipError_t launch_q27_f32(const Launch& L, hipStream_t s) { return launch_tu<27, StoreF32>(L, s); }
+hipError_t launch_q27_f32(const Launch& L, hipStream_t s) { return launch_tu<27, StoreF32>(L, s, launch_q27_f32_mrt); }
 }  // namespace lbm

@@ -136,7 +136,7 @@ __device__ __forceinline__ bool is_fluid(const Field& F, uint32_t j) { return (F
 template <class R>
 __device__ __forceinline__ Relax<R> relax_of(const RelaxD& p)
 {
-    return Relax<R>{R(p.omega), R(p.omega_m), R(p.omega_b)};
+    return Relax<R>{R(p.omega), R(p.omega_m), R(p.omega_b), R(p.omega3), R(p.omega4)};
 }
 
 // Loads never wait for the flag byte: every lane issues its population loads
@@ -460,7 +460,7 @@ __device__ __forceinline__ uint32_t step_block()
 
 // Fast part over every cell of the lattice.
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
-__global__ void __launch_bounds__(1024) LBM_STEP_ATTR k_step(Field F, RelaxD pd)
+__global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) LBM_STEP_ATTR k_step(Field F, RelaxD pd)
 {
     const uint32_t i = step_block() * blockDim.x + threadIdx.x;
     if (i >= F.ntot) return;
@@ -550,7 +550,7 @@ __global__ void __launch_bounds__(256) LBM_STEP_ATTR k_step_vec(Field F, RelaxD 
 // Fast and slow parts in one pass over every cell (one launch per step, as
 // the per-cavity reference path of the batched ensemble uses).
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
-__global__ void __launch_bounds__(1024) k_step_all(Field F, RelaxD pd)
+__global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) k_step_all(Field F, RelaxD pd)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= F.ntot) return;
@@ -572,7 +572,7 @@ __global__ void __launch_bounds__(256) k_step_slow(Field F, RelaxD pd, const uin
 // ---------------------------------------------------------------------------
 // Batched ensemble: one launch over a table of (cavity, first cell) tiles.
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
-__global__ void __launch_bounds__(1024) k_step_batch(const BatchCavity* __restrict__ cav,
+__global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) k_step_batch(const BatchCavity* __restrict__ cav,
                                                      const uint32_t* __restrict__ tiles)
 {
     const uint32_t t = tiles[blockIdx.x];

@@ -289,13 +289,17 @@ static int validate(const lbm_desc* d)
     if (d->layout == LBM_SOA && (uint64_t)n * elem_bytes(d->storage_dtype) >= (1ull << 32))
         return fail(LBM_EUNSUPPORTED, "SoA streams above 4 GiB (cells x bytes per value) are not supported");
     if (d->scheme < LBM_2POP || d->scheme > LBM_AA) return fail(LBM_EINVAL, "unknown scheme");
-    if (d->collision < LBM_BGK || d->collision > LBM_RR) return fail(LBM_EINVAL, "unknown collision model");
+    if (d->collision < LBM_BGK || d->collision > LBM_K) return fail(LBM_EINVAL, "unknown collision model");
+    if (d->collision == LBM_K && d->lattice != 19)
+        return fail(LBM_EUNSUPPORTED, "the cumulant model is defined on D3Q19 only");
     if (d->storage_dtype < LBM_F64 || d->storage_dtype > LBM_F16_SHIFTED) return fail(LBM_EINVAL, "unknown storage dtype");
     if (d->layout != LBM_SOA && d->layout != LBM_AOS) return fail(LBM_EINVAL, "unknown layout");
     if (d->geometry < LBM_CAVITY || d->geometry > LBM_CHANNEL) return fail(LBM_EINVAL, "unknown geometry");
     if (d->ptr_kind != LBM_PTR_DEVICE && d->ptr_kind != LBM_PTR_HOST) return fail(LBM_EINVAL, "unknown pointer kind");
     if (!(d->omega > 0.0 && d->omega < 2.0)) return fail(LBM_EINVAL, "omega must lie in (0, 2)");
     if (d->omega_bulk > 0.0 && !(d->omega_bulk < 2.0)) return fail(LBM_EINVAL, "omega_bulk must lie in (0, 2)");
+    if (d->omega3 > 0.0 && !(d->omega3 < 2.0)) return fail(LBM_EINVAL, "omega3 must lie in (0, 2)");
+    if (d->omega4 > 0.0 && !(d->omega4 < 2.0)) return fail(LBM_EINVAL, "omega4 must lie in (0, 2)");
     if (d->collision == LBM_TRT && !(d->trt_lambda > 0.0)) return fail(LBM_EINVAL, "trt_lambda must be > 0");
     const double* v = d->lid_velocity;
     if (!(std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) < 0.4)) return fail(LBM_EINVAL, "|lid velocity| must be < 0.4");
@@ -432,6 +436,7 @@ static int autotune(lbm_handle* h)
     float best = 1e30f;
     int best_b = 256;
     for (int c : cand) {
+        if (c > max_step_block(h->d.lattice, h->d.collision, (int)elem_bytes(h->d.storage_dtype))) continue;
         h->block = c;
         int rc = enqueue_steps(h, 2);
         if (rc) return rc;
@@ -463,10 +468,12 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
     h->stride = d->layout == LBM_SOA ? soa_stride(h->ntot) : h->ntot;
     h->stream = (hipStream_t)d->stream;
     h->launch = pick_tu(d->lattice, d->storage_dtype);
-    h->block = d->block_size > 0 ? d->block_size : 256;
+    h->block = std::min(d->block_size > 0 ? d->block_size : 256, max_step_block(d->lattice, d->collision, (int)elem_bytes(d->storage_dtype)));
     h->relax.omega = d->omega;
     h->relax.omega_m = d->collision == LBM_TRT ? trt_omega_minus(d->omega, d->trt_lambda) : d->omega;
     h->relax.omega_b = d->omega_bulk > 0.0 ? d->omega_bulk : d->omega;
+    h->relax.omega3 = d->omega3 > 0.0 ? d->omega3 : 1.0;
+    h->relax.omega4 = d->omega4 > 0.0 ? d->omega4 : 1.0;
     size_t req[3];
     lbm_required_bytes(d, req);
     h->pop_bytes = req[0];

@@ -21,7 +21,8 @@ LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(HERE, "liblbm.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 SCHEMES = {"2pop": 0, "swap": 1, "aa": 2}
-COLLISIONS = {"bgk": 0, "trt": 1, "reg": 2, "rr": 3}
+COLLISIONS = {"bgk": 0, "trt": 1, "reg": 2, "rr": 3,
+              "nw4": 4, "rm": 5, "hm": 6, "cm": 7, "chm": 8, "k": 9}
 DTYPES = {"f64": 0, "f32": 1, "f16": 2}
 LAYOUTS = {"soa": 0, "aos": 1}
 GEOMETRIES = {"cavity": 0, "periodic": 1, "channel": 2}
@@ -40,6 +41,7 @@ class Desc(ctypes.Structure):
                 ("layout", ctypes.c_int), ("geometry", ctypes.c_int), ("ptr_kind", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("block_size", ctypes.c_int),
                 ("omega", ctypes.c_double), ("trt_lambda", ctypes.c_double), ("omega_bulk", ctypes.c_double),
+                ("omega3", ctypes.c_double), ("omega4", ctypes.c_double),
                 ("lid_velocity", ctypes.c_double * 3), ("stream", ctypes.c_void_p),
                 ("pop", ctypes.c_void_p), ("out", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
 
@@ -175,7 +177,8 @@ class Lattice:
                  scheme: str = "aa", collision: str = "bgk", omega: float = 1.0, u_lid: float = 0.0,
                  dtype: str = "f64", layout: str = "soa", geometry: str = "cavity", trt_lambda: float = 0.25,
                  omega_bulk: float | None = None, lid_velocity=None, check_every: int = 0,
-                 block_size: int = 0, device: int | str | torch.device = 0):
+                 block_size: int = 0, device: int | str | torch.device = 0,
+                 omega3: float | None = None, omega4: float | None = None):
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         ny = nx if ny is None else ny
         nz = nx if nz is None else nz
@@ -186,6 +189,8 @@ class Lattice:
         d.storage_dtype, d.layout, d.geometry = DTYPES[dtype], LAYOUTS[layout], GEOMETRIES[geometry]
         d.omega, d.trt_lambda = omega, trt_lambda
         d.omega_bulk = 0.0 if omega_bulk is None else omega_bulk
+        d.omega3 = 0.0 if omega3 is None else omega3
+        d.omega4 = 0.0 if omega4 is None else omega4
         lv = (u_lid, 0.0, 0.0) if lid_velocity is None else tuple(lid_velocity)
         for a in range(3):
             d.lid_velocity[a] = lv[a]

@@ -51,7 +51,8 @@ def _desc(hiplib, **kw):
 
 @pytest.mark.parametrize("field,value,needle", [
     ("lattice", 20, "lattice"), ("nx", 2, "dimensions"), ("omega", 2.0, "omega"), ("omega", 0.0, "omega"),
-    ("scheme", 7, "scheme"), ("collision", 9, "collision"), ("storage_dtype", 5, "dtype"),
+    ("scheme", 7, "scheme"), ("collision", 10, "collision"), ("storage_dtype", 5, "dtype"),
+    ("omega3", 2.5, "omega3"), ("omega4", 2.0, "omega4"), ("omega_bulk", 2.0, "omega_bulk"),
     ("layout", 3, "layout"), ("block_size", 96, "block_size"), ("check_every", -1, "check_every"),
 ])
 def test_invalid_descriptions_are_rejected(hiplib, field, value, needle):
@@ -60,6 +61,15 @@ def test_invalid_descriptions_are_rejected(hiplib, field, value, needle):
     assert hiplib.lib().lbm_required_bytes(ctypes.byref(d), out) == hiplib.EINVAL
     assert needle in hiplib.last_error()
     assert not hiplib.lib().lbm_create_ex(ctypes.byref(d))
+
+
+def test_cumulant_model_is_d3q19_only(hiplib):
+    d = _desc(hiplib, lattice=27, collision=9)
+    out = (ctypes.c_size_t * 3)()
+    assert hiplib.lib().lbm_required_bytes(ctypes.byref(d), out) == hiplib.EUNSUPPORTED
+    assert "cumulant" in hiplib.last_error()
+    d = _desc(hiplib, lattice=19, collision=9, omega3=1.5, omega4=0.5)
+    assert hiplib.lib().lbm_required_bytes(ctypes.byref(d), out) == 0
 
 
 def test_fast_lid_is_rejected(hiplib):
