@@ -41,8 +41,20 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str, objdir: str = OBJDIR, defines=()) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """True if obj is older than its source or any header it may include."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src)] + [os.path.join(d, f) for d in (CSRC, INCLUDE)
+                                        for f in os.listdir(d) if f.endswith((".hpp", ".h"))]
+    return any(os.path.getmtime(p) > t for p in deps)
+
+
+def _compile(src: str, objdir: str = OBJDIR, defines=(), incremental: bool = False) -> str:
     obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+    if incremental and not _stale(src, obj):
+        return obj
     cmd = [HIPCC, *CFLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -50,17 +62,20 @@ def _compile(src: str, objdir: str = OBJDIR, defines=()) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False, defines=(), out: str | None = None) -> str:
+def build(jobs: int | None = None, verbose: bool = False, defines=(), out: str | None = None,
+          incremental: bool = False) -> str:
     """Compile every translation unit and link liblbm.so; returns its path.
 
     `defines` are extra preprocessor definitions (NAME=VALUE) and `out` an
-    alternative library path, for building tuning variants side by side."""
+    alternative library path, for building tuning variants side by side.
+    `incremental` skips translation units whose object is newer than every
+    source and header (development rebuilds; the default compiles all)."""
     out = out or LIB
     objdir = OBJDIR if out == LIB else out + ".objs"
     os.makedirs(objdir, exist_ok=True)
     jobs = jobs or min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda src: _compile(src, objdir, defines), SOURCES))
+        objs = list(ex.map(lambda src: _compile(src, objdir, defines, incremental), SOURCES))
     tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -73,5 +88,5 @@ def build(jobs: int | None = None, verbose: bool = False, defines=(), out: str |
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

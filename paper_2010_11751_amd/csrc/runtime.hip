@@ -228,6 +228,12 @@ struct lbm_handle {
     hipStream_t aux = nullptr;      // runs the near-wall part beside the fast part
     hipEvent_t fork = nullptr, join = nullptr;
     LaunchFn launch = nullptr;
+    bool use_graph = false;         // small lattice: replay captured steps
+    bool fused = false;             // one kernel per kind (fast and edge parts together)
+    hipStream_t cap = nullptr;      // private stream the step graph is captured on
+    hipGraphExec_t graph = nullptr;
+    int graph_phase = -1;           // AA phase and 2Pop buffer the graph starts from
+    void* graph_pop = nullptr;
 
     Field field() const
     {
@@ -353,6 +359,10 @@ static int run_kind(lbm_handle* h, int kind)
 {
     Launch L = h->base(OP_STEP);
     L.kind = kind;
+    if (h->fused && kind != KIND_SWAP_COLLIDE && kind != KIND_SWAP_STREAM) {
+        L.op = OP_STEP_ALL;
+        return run(h, L);
+    }
     const int cpt = h->cpt;
     if (cpt > 1) {  // the vector kernels are compiled for blocks of at most 256
         L.block = std::min(h->block, 256);
@@ -425,6 +435,74 @@ static int enqueue_steps(lbm_handle* h, int n)
         ++h->steps;
     }
     return LBM_OK;
+}
+
+// Small lattices: a step is a few microseconds of GPU work, less than the
+// host needs to issue its launches one by one, so the steps are captured once
+// in a HIP graph and replayed. A graph holds an even number of steps, so the
+// 2Pop buffers and the AA phase come back to where they started. Inside it
+// every kernel runs on one stream, and on D3Q19 SoA each kind is a single
+// kernel that handles the fast and the edge cells together.
+static constexpr int kGraphSteps = 64;
+static constexpr int64_t kGraphCells = int64_t(1) << 20;
+
+static int capture_steps(lbm_handle* h)
+{
+    if (h->graph) {
+        hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    const int phase0 = h->aa_phase;
+    void* const pop0 = h->pop;
+    void* const out0 = h->out;
+    const int64_t steps0 = h->steps;
+    hipStream_t const user = h->stream, aux = h->aux;
+    h->stream = h->cap;
+    h->aux = nullptr;
+    // One launch per step where a fused kernel exists (D3Q19 SoA, one cell per lane).
+    h->fused = h->q == 19 && h->d.layout == LBM_SOA && h->cpt == 1;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+    int rc = LBM_OK;
+    hipError_t e_end = e;
+    if (e == hipSuccess) {
+        rc = enqueue_steps(h, kGraphSteps);
+        e_end = hipStreamEndCapture(h->cap, &g);
+    }
+    // The capture only recorded launches: put the host-side state back.
+    h->fused = false;
+    h->stream = user;
+    h->aux = aux;
+    h->aa_phase = phase0;
+    h->pop = pop0;
+    h->out = out0;
+    h->steps = steps0;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    if (rc || e_end != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return rc ? rc : hip_fail(e_end, "hipStreamEndCapture");
+    }
+    e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    h->graph_phase = phase0;
+    h->graph_pop = pop0;
+    return LBM_OK;
+}
+
+static int enqueue_steps_graph(lbm_handle* h, int n)
+{
+    while (n >= kGraphSteps) {
+        if (!h->graph || h->graph_phase != h->aa_phase || h->graph_pop != h->pop) {
+            int rc = capture_steps(h);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipGraphLaunch(h->graph, h->stream), "hipGraphLaunch");
+        h->steps += kGraphSteps;
+        n -= kGraphSteps;
+    }
+    return enqueue_steps(h, n);
 }
 
 static int autotune(lbm_handle* h)
@@ -573,6 +651,7 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join, hipEventDisableTiming);
         if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("auxiliary stream: ") + hipGetErrorString(e));
     }
+    h->use_graph = h->ntot <= kGraphCells && !std::getenv("LBM_NO_GRAPH");
     if (init_state(h, nullptr, nullptr)) return bail(LBM_EDEVICE, lbm_last_error());
     if (d->block_size == -1) {
         if (autotune(h) || init_state(h, nullptr, nullptr)) return bail(LBM_EDEVICE, lbm_last_error());
@@ -605,6 +684,8 @@ void lbm_destroy(lbm_handle* h)
     if (h->stream) hipStreamSynchronize(h->stream);
     else hipDeviceSynchronize();
     if (h->aux) hipStreamSynchronize(h->aux);
+    if (h->graph) hipGraphExecDestroy(h->graph);
+    if (h->cap) hipStreamDestroy(h->cap);
     if (h->own_pop && h->pop_alloc) hipFree(h->pop_alloc);
     if (h->own_out && h->out_alloc) hipFree(h->out_alloc);
     if (h->own_flags && h->flags) hipFree(h->flags);
@@ -699,7 +780,7 @@ int lbm_step(lbm_handle* h, int n)
     while (n > 0) {
         int chunk = n;
         if (K > 0) chunk = std::min<int64_t>(n, K - (h->steps % K));
-        int rc = enqueue_steps(h, chunk);
+        int rc = h->use_graph && K == 0 ? enqueue_steps_graph(h, chunk) : enqueue_steps(h, chunk);
         if (rc) return rc;
         n -= chunk;
         if (K > 0 && h->steps % K == 0) {
