@@ -22,12 +22,13 @@ hipError_t launch_step_kind(const Launch& L, hipStream_t s)
         }
         return hipGetLastError();
     }
+    const uint32_t lds = L.lds;
     switch (L.kind) {
-    case KIND_2POP: k_step<Q, MODEL, ST, LAYOUT, KIND_2POP><<<g, b, 0, s>>>(L.F, L.relax); break;
-    case KIND_SWAP_COLLIDE: k_step<Q, MODEL, ST, LAYOUT, KIND_SWAP_COLLIDE><<<g, b, 0, s>>>(L.F, L.relax); break;
-    case KIND_SWAP_STREAM: k_step<Q, BGK, ST, LAYOUT, KIND_SWAP_STREAM><<<g, b, 0, s>>>(L.F, L.relax); break;
-    case KIND_AA_EVEN: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_EVEN><<<g, b, 0, s>>>(L.F, L.relax); break;
-    case KIND_AA_ODD: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, 0, s>>>(L.F, L.relax); break;
+    case KIND_2POP: k_step<Q, MODEL, ST, LAYOUT, KIND_2POP><<<g, b, lds, s>>>(L.F, L.relax); break;
+    case KIND_SWAP_COLLIDE: k_step<Q, MODEL, ST, LAYOUT, KIND_SWAP_COLLIDE><<<g, b, lds, s>>>(L.F, L.relax); break;
+    case KIND_SWAP_STREAM: k_step<Q, BGK, ST, LAYOUT, KIND_SWAP_STREAM><<<g, b, lds, s>>>(L.F, L.relax); break;
+    case KIND_AA_EVEN: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_EVEN><<<g, b, lds, s>>>(L.F, L.relax); break;
+    case KIND_AA_ODD: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, lds, s>>>(L.F, L.relax); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

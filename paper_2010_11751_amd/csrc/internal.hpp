@@ -113,6 +113,7 @@ struct Launch {
     const uint32_t* tiles;
     const uint32_t* slow_list;  // STEP_SLOW: fluid cells off the fast path
     uint32_t n_slow;
+    uint32_t lds;          // STEP: dynamic LDS bytes per block (caps blocks per CU)
 };
 
 hipError_t launch_q19_f64(const Launch& L, hipStream_t s);

@@ -228,6 +228,9 @@ struct lbm_handle {
     hipStream_t aux = nullptr;      // runs the near-wall part beside the fast part
     hipEvent_t fork = nullptr, join = nullptr;
     LaunchFn launch = nullptr;
+    bool lds_override = false;      // LBM_STEP_LDS given: fixed dynamic LDS of the fast
+    uint32_t lds_local = 0;         //   kernels of local kinds
+    uint32_t lds_neighbour = 0;     //   and of the kinds that reach neighbours
     bool use_graph = false;         // small lattice: replay captured steps
     bool fused = false;             // one kernel per kind (fast and edge parts together)
     hipStream_t cap = nullptr;      // private stream the step graph is captured on
@@ -355,10 +358,40 @@ static int init_state(lbm_handle* h, const double* rho, const double* u)
 
 // One kernel kind over the lattice: the fast part over all cells, then, for
 // the kinds that reach neighbours, the slow part over the listed cells.
+// Resident waves per SIMD the fast step kernels are held to (0: no limit),
+// by bytes per stored value and kind. Measured on the 256^3 cavity: with FP64
+// storage every wave keeps 38 streams of 512 B in flight, and two to three
+// waves per SIMD move more bytes per second than the six the registers allow
+// (AA: 15.2 -> 16.5 k MLUPS; 2Pop: 14.2 -> 15.2 k); FP32 gains with four on
+// the kinds that touch only their own cell and 2Pop, and FP16 needs every
+// wave it can get.
+static int step_waves(int elem_bytes, int kind)
+{
+    if (elem_bytes == 8) return kind == KIND_AA_ODD ? 3 : 2;
+    if (elem_bytes == 4) return (kind == KIND_AA_ODD || kind == KIND_SWAP_STREAM) ? 0 : 4;
+    return 0;
+}
+
+// Dynamic LDS per block that leaves room for the wanted number of blocks of
+// the given size on a CU (160 KiB of LDS, at most 64 KiB per block, so at
+// least two blocks). The size sits half a block's share below the limit, so
+// the count holds whatever the allocation granularity. The kernels do not
+// use it: it only caps residency.
+static uint32_t step_lds(const lbm_handle* h, int kind)
+{
+    if (h->lds_override) return kind == KIND_AA_ODD || kind == KIND_2POP || kind == KIND_SWAP_STREAM
+                                    ? h->lds_neighbour : h->lds_local;
+    const int w = step_waves((int)elem_bytes(h->d.storage_dtype), kind);
+    if (w <= 0) return 0;
+    const int blocks = std::max(2, w * 256 / std::max(h->block, 64));
+    return std::min<uint32_t>(65536u, (2u * 163840u / (2u * (uint32_t)blocks + 1u)) / 1024u * 1024u);
+}
+
 static int run_kind(lbm_handle* h, int kind)
 {
     Launch L = h->base(OP_STEP);
     L.kind = kind;
+    L.lds = step_lds(h, kind);
     if (h->fused && kind != KIND_SWAP_COLLIDE && kind != KIND_SWAP_STREAM) {
         L.op = OP_STEP_ALL;
         return run(h, L);
@@ -405,6 +438,7 @@ static int run_kind_overlapped(lbm_handle* h, int kind)
     HIP_TRY(hipEventRecord(h->join, h->aux), "hipEventRecord");
     Launch L = h->base(OP_STEP);
     L.kind = kind;
+    L.lds = step_lds(h, kind);
     if (h->cpt > 1) {
         L.block = std::min(h->block, 256);
         L.grid = grid_for(((uint64_t)h->ntot + h->cpt - 1) / h->cpt, L.block);
@@ -652,6 +686,13 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
         if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("auxiliary stream: ") + hipGetErrorString(e));
     }
     h->use_graph = h->ntot <= kGraphCells && !std::getenv("LBM_NO_GRAPH");
+    if (const char* e = std::getenv("LBM_STEP_LDS")) {  // "bytes" or "local,neighbour"
+        unsigned a = 0, b = 0;
+        const int got = std::sscanf(e, "%u,%u", &a, &b);
+        h->lds_override = got >= 1;
+        h->lds_local = got >= 1 ? std::min(a, 65536u) : 0;
+        h->lds_neighbour = got >= 2 ? std::min(b, 65536u) : h->lds_local;
+    }
     if (init_state(h, nullptr, nullptr)) return bail(LBM_EDEVICE, lbm_last_error());
     if (d->block_size == -1) {
         if (autotune(h) || init_state(h, nullptr, nullptr)) return bail(LBM_EDEVICE, lbm_last_error());
