@@ -102,6 +102,7 @@ def lib():
         L.oracle_equilibrium.restype = None
         L.oracle_collide.argtypes = [cfgp, P, P]
         L.oracle_init_state.argtypes = [cfgp, P, P, P, P]
+        L.oracle_init_state_ex.argtypes = [cfgp, P, P, P, P, P, P]
         L.oracle_reference_step.argtypes = [cfgp, P, P, P]
         L.oracle_reference_cells.argtypes = [cfgp, P, P, P, ctypes.c_int64, P]
         L.oracle_2pop_step.argtypes = [cfgp, P, P, P, P]
@@ -156,12 +157,17 @@ def collide(cfg: Config, f) -> np.ndarray:
     return out
 
 
-def init_state(cfg: Config, fl: np.ndarray, rho=None, u=None) -> np.ndarray:
-    """Wall terms in wall cells, E(rho, u) in fluid cells; u is u[3][Ntot]."""
+def init_state(cfg: Config, fl: np.ndarray, rho=None, u=None, wall_u=None, wall_rho=None) -> np.ndarray:
+    """Wall terms in wall cells (from the lid velocity, or from per-cell
+    wall_u[3][Ntot] and wall_rho[Ntot] when given), E(rho, u) in fluid cells;
+    u is u[3][Ntot]."""
     pop = np.zeros(cfg.ntot * cfg.q)
-    r = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64).ravel()
-    v = None if u is None else np.ascontiguousarray(u, dtype=np.float64).ravel()
-    _check(lib().oracle_init_state(ctypes.byref(cfg.c_struct()), _p(fl), _p(r), _p(v), _p(pop)))
+
+    def arr(a):
+        return None if a is None else np.ascontiguousarray(a, dtype=np.float64).ravel()
+    r, v, wu, wr = arr(rho), arr(u), arr(wall_u), arr(wall_rho)
+    _check(lib().oracle_init_state_ex(ctypes.byref(cfg.c_struct()), _p(fl), _p(r), _p(v), _p(wu), _p(wr),
+                                      _p(pop)))
     return pop
 
 
@@ -224,10 +230,14 @@ class Simulation:
     """Runs the oracle with one of the three schemes of Table 1 and reads back
     the natural pre-collision populations f[k][Ntot] at whole steps."""
 
-    def __init__(self, cfg: Config, scheme: str = "2pop", rho=None, u=None, order=None):
+    def __init__(self, cfg: Config, scheme: str = "2pop", rho=None, u=None, order=None, cell_types=None,
+                 wall_u=None, wall_rho=None):
+        """cell_types (uint8 FLUID / WALL / LID per cell) replaces the
+        geometry's flags; wall_u[3][Ntot] and wall_rho[Ntot] give each wall
+        cell its own velocity and density."""
         self.cfg, self.scheme, self.order = cfg, scheme, order
-        self.flags = flags(cfg)
-        self.pop = init_state(cfg, self.flags, rho, u)
+        self.flags = flags(cfg) if cell_types is None else np.ascontiguousarray(cell_types, dtype=np.uint8).copy()
+        self.pop = init_state(cfg, self.flags, rho, u, wall_u, wall_rho)
         self.out = self.pop.copy() if scheme == "2pop" else None
         self.t = 0
 

@@ -633,8 +633,8 @@ int oracle_collide(const ocfg *g, const double *f, double *fout)
  * (Eq. storage2), fluid cells hold E(rho, u) (Eq. storage1). rho and u may be
  * NULL (rho = 1, u = 0); u is given as u[3][Ntot]. The equilibrium is the
  * model's own (E^S for RR, the NW4 equilibrium for the moment-space models). */
-int oracle_init_state(const ocfg *g, const uint8_t *flags, const double *rho,
-                      const double *u, double *pop)
+int oracle_init_state_ex(const ocfg *g, const uint8_t *flags, const double *rho, const double *u,
+                         const double *wall_u, const double *wall_rho, double *pop)
 {
     olat L;
     int64_t i, n = ntot(g);
@@ -642,7 +642,18 @@ int oracle_init_state(const ocfg *g, const uint8_t *flags, const double *rho,
     if (make_lattice(g->q, &L)) return -1;
     for (i = 0; i < n; ++i) {
         if (flags[i] != O_FLUID) {
-            for (k = 0; k < L.q; ++k) pop[at(g, i, k)] = wall_term(&L, g, flags[i], k);
+            /* Eq. storage2 with the cell's own wall velocity and density when
+             * given: -6 t_k rho_w c_k . u_w. */
+            for (k = 0; k < L.q; ++k) {
+                if (wall_u || wall_rho) {
+                    double uw[3] = {0.0, 0.0, 0.0}, rw = wall_rho ? wall_rho[i] : 1.0;
+                    if (wall_u) { uw[0] = wall_u[i]; uw[1] = wall_u[n + i]; uw[2] = wall_u[2 * n + i]; }
+                    pop[at(g, i, k)] = -6.0 * L.t[k] * rw *
+                                       (L.c[k][0] * uw[0] + L.c[k][1] * uw[1] + L.c[k][2] * uw[2]);
+                } else {
+                    pop[at(g, i, k)] = wall_term(&L, g, flags[i], k);
+                }
+            }
         } else {
             double r = rho ? rho[i] : 1.0, v[3] = {0.0, 0.0, 0.0}, E[27];
             if (u) { v[0] = u[i]; v[1] = u[n + i]; v[2] = u[2 * n + i]; }
@@ -655,13 +666,21 @@ int oracle_init_state(const ocfg *g, const uint8_t *flags, const double *rho,
     return 0;
 }
 
+int oracle_init_state(const ocfg *g, const uint8_t *flags, const double *rho,
+                      const double *u, double *pop)
+{
+    return oracle_init_state_ex(g, flags, rho, u, NULL, NULL, pop);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Reference step, free of any memory-access scheme (Sec. 2.1):
  * collide every fluid cell, then every fluid cell x gathers population k from
  * its upstream neighbour s = x - c_k; if s is not fluid the link is bounced
  * back at the half-way wall, f_k(x) = f_out_kbar(x) + w_kbar(s)
- * (Eq. momentum-exchange with k and k-bar exchanged). The rest population
- * stays. Wall cells keep their stored terms. fnew must not alias f. */
+ * (Eq. momentum-exchange with k and k-bar exchanged), w_kbar(s) being the
+ * term the wall cell s stores in its slot k-bar (Eq. storage2). The rest
+ * population stays. Wall cells keep their stored terms. fnew must not alias
+ * f. */
 int oracle_reference_step(const ocfg *g, const uint8_t *flags, const double *f, double *fnew)
 {
     olat L;
@@ -693,7 +712,7 @@ int oracle_reference_step(const ocfg *g, const uint8_t *flags, const double *f, 
             if (k == L.rest) { fnew[at(g, i, k)] = fo[at(g, i, k)]; continue; }
             s = neighbour(g, i, L.c[k], -1);
             if (flags[s] == O_FLUID) fnew[at(g, i, k)] = fo[at(g, s, k)];
-            else fnew[at(g, i, k)] = fo[at(g, i, L.opp[k])] + wall_term(&L, g, flags[s], L.opp[k]);
+            else fnew[at(g, i, k)] = fo[at(g, i, L.opp[k])] + f[at(g, s, L.opp[k])];
         }
     }
     free(fo);
@@ -728,7 +747,7 @@ int oracle_reference_cells(const ocfg *g, const uint8_t *flags, const double *f,
                 collide(&L, g, cell, out);
                 fnew[j * L.q + k] = out[k];
             } else {
-                fnew[j * L.q + k] = own[L.opp[k]] + wall_term(&L, g, flags[s], L.opp[k]);
+                fnew[j * L.q + k] = own[L.opp[k]] + f[at(g, s, L.opp[k])];
             }
         }
     }
