@@ -152,6 +152,22 @@ void lbm_destroy(lbm_handle *h);
  * AA phase and the step counter. */
 int lbm_init_equilibrium(lbm_handle *h, const double *rho, const double *u);
 
+/* Replace the geometry by caller cell types (Sec. 2.1: link-wise bounce-back
+ * Dirichlet walls with the momentum-exchange term of Eq. momentum-exchange,
+ * stored in the wall cells as Eq. storage2). type[Ntot] holds LBM_FLUID,
+ * LBM_WALL or LBM_LID per cell (LID is a wall like any other here). Each wall
+ * cell stores -6 t_k rho_w c_k . u_w from its own wall velocity
+ * wall_velocity[3][Ntot] (SoA; NULL: at rest) and wall density
+ * wall_density[Ntot] (NULL: 1); values of fluid cells are ignored. The box
+ * faces of axes that do not wrap (all of them for LBM_CAVITY, z for
+ * LBM_CHANNEL) must be walls; |u_w| < 0.4 and 0 < rho_w < 10. Otherwise
+ * returns LBM_EINVAL and leaves the handle unchanged. On success the fluid
+ * cells are reset to E(1, 0), the AA phase and step counter to zero, and
+ * later lbm_init_equilibrium calls keep these wall terms. Pointers follow
+ * ptr_kind; the caller keeps ownership. */
+int lbm_set_geometry(lbm_handle *h, const uint8_t *type, const double *wall_velocity,
+                     const double *wall_density);
+
 /* Advance n >= 0 time steps (asynchronous on the handle's stream unless the
  * invariant monitor is on). AA phase is tracked, so any n is allowed.
  * Returns LBM_ENONFINITE if the monitor finds a non-finite mass or energy. */

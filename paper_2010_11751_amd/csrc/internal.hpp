@@ -82,6 +82,9 @@ struct InitArgs {
     const double* rho;     // device, may be null
     const double* u;       // device [3][ntot], may be null
     double lid[3];
+    const double* wall_u;    // device [3][ntot]: per-cell wall velocity, may be null
+    const double* wall_rho;  // device [ntot]: per-cell wall density, may be null
+    int keep_walls;          // leave the stored terms of wall cells untouched
 };
 
 struct BatchCavity {

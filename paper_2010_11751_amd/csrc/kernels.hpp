@@ -702,8 +702,10 @@ __device__ __forceinline__ double wall_term(uint8_t type, const double (&lid)[3]
 }
 
 // Fluid cells: the model's equilibrium at (rho, u) (rho = 1, u = 0 when the
-// pointers are null). Wall cells: wall terms. Written to pop and, if not null,
-// to out.
+// pointers are null). Wall cells: the momentum-exchange terms of Eq. storage2,
+// -6 t_k rho_w c_k . u_w, from the per-cell wall velocity and density when
+// given, else from the lid velocity on lid cells (rho_w = 1); with keep_walls
+// they keep what they store. Written to pop and, if not null, to out.
 template <int Q, int MODEL, class ST, int LAYOUT>
 __global__ void k_init(Field F, InitArgs ia)
 {
@@ -713,8 +715,24 @@ __global__ void k_init(Field F, InitArgs ia)
     const uint8_t type = F.flags[i] & FL_TYPE;
     R g[Q];
     if (type != FL_FLUID) {
-        const double lid[3] = {ia.lid[0], ia.lid[1], ia.lid[2]};
-        static_for<0, Q>([&](auto K) { g[K] = R(wall_term<Q, K>(type, lid)); });
+        if (ia.keep_walls) return;
+        if (ia.wall_u || ia.wall_rho) {
+            const double rw = ia.wall_rho ? ia.wall_rho[i] : 1.0;
+            double uw[3] = {0.0, 0.0, 0.0};
+            if (ia.wall_u) {
+                uw[0] = ia.wall_u[i];
+                uw[1] = ia.wall_u[(size_t)F.ntot + i];
+                uw[2] = ia.wall_u[2 * (size_t)F.ntot + i];
+            }
+            static_for<0, Q>([&](auto K) {
+                constexpr int k = K;
+                const double cu = L<Q>::cx(k) * uw[0] + L<Q>::cy(k) * uw[1] + L<Q>::cz(k) * uw[2];
+                g[k] = R(-6.0 * L<Q>::t(k) * rw * cu);
+            });
+        } else {
+            const double lid[3] = {ia.lid[0], ia.lid[1], ia.lid[2]};
+            static_for<0, Q>([&](auto K) { g[K] = R(wall_term<Q, K>(type, lid)); });
+        }
     } else {
         const R rho = ia.rho ? R(ia.rho[i]) : R(1);
         R u[3] = {R(0), R(0), R(0)};

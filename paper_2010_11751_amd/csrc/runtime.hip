@@ -148,6 +148,41 @@ __global__ void k_flag_types_only(const uint8_t* fl, uint8_t* out, uint64_t n)
     if (i < n) out[i] = fl[i] & FL_TYPE;
 }
 
+// Caller cell types: count the cells that break the rules (type not FLUID /
+// WALL / LID; a fluid cell on a box face whose axis does not wrap; a wall
+// velocity of magnitude >= 0.4 or a wall density outside (0, 10)).
+__global__ void k_check_geometry(const uint8_t* type, const double* wu, const double* wr, int nx, int ny, int nz,
+                                 int wrap_x, int wrap_y, int wrap_z, unsigned long long* bad)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = (uint64_t)nx * ny * nz;
+    bool err = false;
+    if (i < n) {
+        const int z = (int)(i % nz), y = (int)((i / nz) % ny), x = (int)(i / ((uint64_t)ny * nz));
+        const uint8_t t = type[i];
+        if (t > FL_LID) err = true;
+        if (t == FL_FLUID) {
+            if (!wrap_x && (x == 0 || x == nx - 1)) err = true;
+            if (!wrap_y && (y == 0 || y == ny - 1)) err = true;
+            if (!wrap_z && (z == 0 || z == nz - 1)) err = true;
+        } else {
+            if (wu) {
+                const double a = wu[i], b = wu[n + i], c = wu[2 * n + i];
+                if (!(a * a + b * b + c * c < 0.16)) err = true;
+            }
+            if (wr && !(wr[i] > 0.0 && wr[i] < 10.0)) err = true;
+        }
+    }
+    const unsigned long long m = __ballot(err);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(bad, (unsigned long long)__popcll(m));
+}
+
+__global__ void k_set_types(const uint8_t* type, uint8_t* fl, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) fl[i] = type[i];
+}
+
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 
 __global__ void k_count_fluid(const uint8_t* fl, uint64_t n, unsigned long long* count)
@@ -231,6 +266,7 @@ struct lbm_handle {
     bool lds_override = false;      // LBM_STEP_LDS given: fixed dynamic LDS of the fast
     uint32_t lds_local = 0;         //   kernels of local kinds
     uint32_t lds_neighbour = 0;     //   and of the kinds that reach neighbours
+    bool custom_walls = false;      // wall terms set per cell (lbm_set_geometry)
     bool use_graph = false;         // small lattice: replay captured steps
     bool fused = false;             // one kernel per kind (fast and edge parts together)
     hipStream_t cap = nullptr;      // private stream the step graph is captured on
@@ -348,6 +384,7 @@ static int init_state(lbm_handle* h, const double* rho, const double* u)
     L.init.rho = rho;
     L.init.u = u;
     for (int a = 0; a < 3; ++a) L.init.lid[a] = h->d.lid_velocity[a];
+    L.init.keep_walls = h->custom_walls ? 1 : 0;
     int rc = run(h, L);
     if (rc) return rc;
     h->aa_phase = 0;
@@ -570,6 +607,55 @@ static int autotune(lbm_handle* h)
     return LBM_OK;
 }
 
+// From the cell types in the flags: the fast-path hints, the fluid-cell
+// count, the ascending list of fluid cells that need the general neighbour /
+// bounce-back path, and the second stream that runs them.
+static int build_tables(lbm_handle* h)
+{
+    const lbm_desc* d = &h->d;
+    const uint32_t g = grid_for((uint64_t)h->ntot, 256);
+    k_flag_hints<<<g, 256, 0, h->stream>>>(h->flags, d->nx, d->ny, d->nz);
+    unsigned long long* cnt = (unsigned long long*)h->partial;
+    k_zero_u64<<<1, 1, 0, h->stream>>>(cnt);
+    k_count_fluid<<<g, 256, 0, h->stream>>>(h->flags, (uint64_t)h->ntot, cnt);
+    unsigned long long nf = 0;
+    HIP_TRY(hipMemcpyAsync(&nf, cnt, sizeof(nf), hipMemcpyDeviceToHost, h->stream), "flag set-up");
+    HIP_TRY(hipStreamSynchronize(h->stream), "flag set-up");
+    h->fluid = (int64_t)nf;
+
+    std::vector<uint8_t> fl((size_t)h->ntot);
+    HIP_TRY(hipMemcpy(fl.data(), h->flags, (size_t)h->ntot, hipMemcpyDeviceToHost), "flag read-back");
+    const int64_t cpt = h->cpt;
+    std::vector<uint32_t> slow;
+    for (int64_t g0 = 0; g0 < h->ntot; g0 += cpt) {
+        // a group is fast when it is whole and every cell in it is a fast fluid cell
+        bool fast = g0 + cpt <= h->ntot;
+        // the vector kernels have no wall-plane path, so those cells are listed too
+        const uint8_t off_path = cpt > 1 ? (FL_TYPE | FL_SLOW | FL_PLANE) : (FL_TYPE | FL_SLOW);
+        for (int64_t i = g0; i < g0 + cpt && i < h->ntot; ++i)
+            fast = fast && (fl[i] & off_path) == FL_FLUID;
+        if (fast) continue;
+        for (int64_t i = g0; i < g0 + cpt && i < h->ntot; ++i)
+            if ((fl[i] & FL_TYPE) == FL_FLUID) slow.push_back((uint32_t)i);
+    }
+    if (h->slow_list) {
+        HIP_TRY(hipFree(h->slow_list), "hipFree");
+        h->slow_list = nullptr;
+    }
+    h->n_slow = (uint32_t)slow.size();
+    if (h->n_slow) {
+        HIP_TRY(hipMalloc((void**)&h->slow_list, sizeof(uint32_t) * slow.size()), "hipMalloc slow list");
+        HIP_TRY(hipMemcpy(h->slow_list, slow.data(), sizeof(uint32_t) * slow.size(), hipMemcpyHostToDevice),
+                "slow list");
+    }
+    if (h->n_slow > 0 && !h->aux && !std::getenv("LBM_NO_OVERLAP")) {
+        HIP_TRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking), "auxiliary stream");
+        HIP_TRY(hipEventCreateWithFlags(&h->fork, hipEventDisableTiming), "auxiliary stream");
+        HIP_TRY(hipEventCreateWithFlags(&h->join, hipEventDisableTiming), "auxiliary stream");
+    }
+    return LBM_OK;
+}
+
 lbm_handle* lbm_create_ex(const lbm_desc* d)
 {
     if (validate(d)) return nullptr;
@@ -637,54 +723,11 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
     if (!alloc((void**)&h->partial, sizeof(double) * (2 * (size_t)h->red_blocks + 2), "reduction"))
         return bail(LBM_ENOMEM, lbm_last_error());
 
-    // Flags: types, then fast-path hints; count fluid cells.
-    const uint32_t g = grid_for((uint64_t)h->ntot, 256);
-    k_flag_types<<<g, 256, 0, h->stream>>>(h->flags, d->nx, d->ny, d->nz, d->geometry);
-    k_flag_hints<<<g, 256, 0, h->stream>>>(h->flags, d->nx, d->ny, d->nz);
-    unsigned long long* cnt = (unsigned long long*)h->partial;
-    k_zero_u64<<<1, 1, 0, h->stream>>>(cnt);
-    k_count_fluid<<<g, 256, 0, h->stream>>>(h->flags, (uint64_t)h->ntot, cnt);
-    unsigned long long nf = 0;
-    hipError_t e = hipMemcpyAsync(&nf, cnt, sizeof(nf), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("flag set-up: ") + hipGetErrorString(e));
-    h->fluid = (int64_t)nf;
-
-    // Fluid cells that need the general neighbour / bounce-back path, in
-    // ascending order.
-    {
-        std::vector<uint8_t> fl((size_t)h->ntot);
-        e = hipMemcpy(fl.data(), h->flags, (size_t)h->ntot, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("flag read-back: ") + hipGetErrorString(e));
-        h->cpt = d->layout == LBM_SOA ? cells_per_thread((int)elem_bytes(d->storage_dtype)) : 1;
-        const int64_t cpt = h->cpt;
-        std::vector<uint32_t> slow;
-        for (int64_t g0 = 0; g0 < h->ntot; g0 += cpt) {
-            // a group is fast when it is whole and every cell in it is a fast fluid cell
-            bool fast = g0 + cpt <= h->ntot;
-            // the vector kernels have no wall-plane path, so those cells are listed too
-            const uint8_t off_path = cpt > 1 ? (FL_TYPE | FL_SLOW | FL_PLANE) : (FL_TYPE | FL_SLOW);
-            for (int64_t i = g0; i < g0 + cpt && i < h->ntot; ++i)
-                fast = fast && (fl[i] & off_path) == FL_FLUID;
-            if (fast) continue;
-            for (int64_t i = g0; i < g0 + cpt && i < h->ntot; ++i)
-                if ((fl[i] & FL_TYPE) == FL_FLUID) slow.push_back((uint32_t)i);
-        }
-        h->n_slow = (uint32_t)slow.size();
-        if (h->n_slow) {
-            if (!alloc((void**)&h->slow_list, sizeof(uint32_t) * slow.size(), "slow list"))
-                return bail(LBM_ENOMEM, lbm_last_error());
-            e = hipMemcpy(h->slow_list, slow.data(), sizeof(uint32_t) * slow.size(), hipMemcpyHostToDevice);
-            if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("slow list: ") + hipGetErrorString(e));
-        }
-    }
-
-    if (h->n_slow > 0 && !std::getenv("LBM_NO_OVERLAP")) {
-        e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join, hipEventDisableTiming);
-        if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("auxiliary stream: ") + hipGetErrorString(e));
-    }
+    // Flags: types, then fast-path hints, fluid count and edge-cell list.
+    k_flag_types<<<grid_for((uint64_t)h->ntot, 256), 256, 0, h->stream>>>(h->flags, d->nx, d->ny, d->nz,
+                                                                          d->geometry);
+    h->cpt = d->layout == LBM_SOA ? cells_per_thread((int)elem_bytes(d->storage_dtype)) : 1;
+    if (int rc = build_tables(h)) return bail(rc, lbm_last_error());
     h->use_graph = h->ntot <= kGraphCells && !std::getenv("LBM_NO_GRAPH");
     if (const char* e = std::getenv("LBM_STEP_LDS")) {  // "bytes" or "local,neighbour"
         unsigned a = 0, b = 0;
@@ -697,7 +740,7 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
     if (d->block_size == -1) {
         if (autotune(h) || init_state(h, nullptr, nullptr)) return bail(LBM_EDEVICE, lbm_last_error());
     }
-    e = hipStreamSynchronize(h->stream);
+    hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("initialisation: ") + hipGetErrorString(e));
     return h;
 }
@@ -792,6 +835,50 @@ int lbm_init_equilibrium(lbm_handle* h, const double* rho, const double* u)
     if (!rc) rc = init_state(h, (const double*)dr, (const double*)du);
     if (!rc && h->d.ptr_kind == LBM_PTR_HOST) HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     return rc;
+}
+
+int lbm_set_geometry(lbm_handle* h, const uint8_t* type, const double* wall_velocity, const double* wall_density)
+{
+    if (!h || !type) return fail(LBM_EINVAL, "null argument");
+    Staging st, su, sr;
+    const void *dt, *du, *dr;
+    int rc = stage_in(h, type, (size_t)h->ntot, st, &dt);
+    if (!rc) rc = stage_in(h, wall_velocity, sizeof(double) * 3 * h->ntot, su, &du);
+    if (!rc) rc = stage_in(h, wall_density, sizeof(double) * h->ntot, sr, &dr);
+    if (rc) return rc;
+    const lbm_desc* d = &h->d;
+    const int wrap = d->geometry == LBM_PERIODIC ? 7 : d->geometry == LBM_CHANNEL ? 3 : 0;
+    const uint32_t g = grid_for((uint64_t)h->ntot, 256);
+    unsigned long long* cnt = (unsigned long long*)h->partial;
+    k_zero_u64<<<1, 1, 0, h->stream>>>(cnt);
+    k_check_geometry<<<g, 256, 0, h->stream>>>((const uint8_t*)dt, (const double*)du, (const double*)dr, d->nx,
+                                               d->ny, d->nz, wrap & 1, (wrap >> 1) & 1, (wrap >> 2) & 1, cnt);
+    unsigned long long bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, cnt, sizeof(bad), hipMemcpyDeviceToHost, h->stream), "geometry check");
+    HIP_TRY(hipStreamSynchronize(h->stream), "geometry check");
+    if (bad)
+        return fail(LBM_EINVAL, std::to_string(bad) + " cells break the geometry rules (types FLUID/WALL/LID; "
+                                "no fluid on a face that does not wrap; |u_w| < 0.4; 0 < rho_w < 10)");
+    if (h->aux) HIP_TRY(hipStreamSynchronize(h->aux), "hipStreamSynchronize");
+    if (h->graph) {  // its launches name the old edge-cell list
+        HIP_TRY(hipGraphExecDestroy(h->graph), "hipGraphExecDestroy");
+        h->graph = nullptr;
+    }
+    k_set_types<<<g, 256, 0, h->stream>>>((const uint8_t*)dt, h->flags, (uint64_t)h->ntot);
+    rc = build_tables(h);
+    if (rc) return rc;
+    Launch L = h->base(OP_INIT);
+    L.init.wall_u = (const double*)du;
+    L.init.wall_rho = (const double*)dr;
+    for (int a = 0; a < 3; ++a) L.init.lid[a] = d->lid_velocity[a];
+    rc = run(h, L);
+    if (rc) return rc;
+    h->custom_walls = true;
+    h->aa_phase = 0;
+    h->steps = 0;
+    h->first_nonfinite = -1;
+    if (d->ptr_kind == LBM_PTR_HOST) HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return LBM_OK;
 }
 
 static int invariants_raw(lbm_handle* h, double* mass, double* ke)

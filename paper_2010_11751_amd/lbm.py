@@ -64,7 +64,7 @@ class BatchOpts(ctypes.Structure):
 
 SYMBOLS = [
     "lbm_desc_default", "lbm_required_bytes", "lbm_create", "lbm_create_ex", "lbm_destroy",
-    "lbm_init_equilibrium", "lbm_step", "lbm_macroscopic", "lbm_get_populations", "lbm_get_populations_at",
+    "lbm_init_equilibrium", "lbm_set_geometry", "lbm_step", "lbm_macroscopic", "lbm_get_populations", "lbm_get_populations_at",
     "lbm_set_populations",
     "lbm_get_flags", "lbm_invariants", "lbm_neighbor_index", "lbm_get_info", "lbm_lattice", "lbm_device_copy",
     "lbm_sync",
@@ -95,6 +95,7 @@ def lib() -> ctypes.CDLL:
     L.lbm_destroy.argtypes = [P]
     L.lbm_destroy.restype = None
     L.lbm_init_equilibrium.argtypes = [P, P, P]
+    L.lbm_set_geometry.argtypes = [P, P, P, P]
     L.lbm_step.argtypes = [P, I]
     L.lbm_macroscopic.argtypes = [P, P, P]
     L.lbm_get_populations.argtypes = [P, P]
@@ -238,6 +239,14 @@ class Lattice:
         r = _dev(rho, torch.float64, self.ntot, self.device)
         v = _dev(u, torch.float64, 3 * self.ntot, self.device)
         check(lib().lbm_init_equilibrium(self.h, _ptr(r), _ptr(v)))
+
+    def set_geometry(self, cell_types, wall_velocity=None, wall_density=None) -> None:
+        """Caller cell types (uint8 FLUID / WALL / LID per cell) with per-cell
+        wall velocity [3][Ntot] and wall density [Ntot] of the wall cells."""
+        t = _dev(cell_types, torch.uint8, self.ntot, self.device)
+        wu = _dev(wall_velocity, torch.float64, 3 * self.ntot, self.device)
+        wr = _dev(wall_density, torch.float64, self.ntot, self.device)
+        check(lib().lbm_set_geometry(self.h, _ptr(t), _ptr(wu), _ptr(wr)))
 
     def sync(self) -> None:
         check(lib().lbm_sync(self.h))
