@@ -122,6 +122,8 @@ struct lbm_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int block = 256;
+    int elem = 8;                   // bytes per stored value
+    bool no_residency_cap = false;  // LBM_NO_RESIDENCY_CAP set: every wave may be resident
     int64_t cells = 0, fluid = 0;
     int phase = 0;  // AA phase, or 2Pop parity (which array is current)
     hipGraphExec_t graph = nullptr;
@@ -166,6 +168,7 @@ int launch_batch_step(lbm_batch* b)
         L.kind = b->phase ? KIND_AA_ODD : KIND_AA_EVEN;
         L.cav = b->d_cav[0];
     }
+    L.lds = b->no_residency_cap ? 0 : residency_lds(step_waves(b->elem, L.kind), b->block);
     hipError_t e = b->launch(L, b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch step launch");
     b->phase ^= 1;
@@ -280,6 +283,8 @@ lbm_batch* lbm_batch_create(int count, const lbm_cavity_desc* d, int scheme, int
     b->count = count;
     b->scheme = scheme;
     b->collision = collision;
+    b->elem = storage_dtype == LBM_F64 ? 8 : storage_dtype == LBM_F32_SHIFTED ? 4 : 2;
+    b->no_residency_cap = std::getenv("LBM_NO_RESIDENCY_CAP") != nullptr;
     b->dtype = storage_dtype;
     b->desc.assign(d, d + count);
     if (opts) b->opts = *opts;

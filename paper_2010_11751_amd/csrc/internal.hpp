@@ -74,6 +74,35 @@ constexpr int max_step_block(int q, int model, int elem_bytes)
     return (model >= 4 || (q == 27 && elem_bytes == 8)) ? 256 : 1024;
 }
 
+// Resident waves per SIMD the fast step kernels are held to (0: no limit),
+// by bytes per stored value and kind. Measured on the 256^3 cavity: with FP64
+// storage every wave keeps 38 streams of 512 B in flight, and two to three
+// waves per SIMD move more bytes per second than the six the registers allow
+// (AA: 15.2 -> 16.5 k MLUPS; 2Pop: 14.2 -> 15.2 k); FP32 gains with four on
+// the kinds that touch only their own cell and 2Pop, and FP16 needs every
+// wave it can get. Kinds: 0 2Pop, 1 swap collide, 2 swap stream, 3 AA even,
+// 4 AA odd.
+inline int step_waves(int elem_bytes, int kind)
+{
+    if (elem_bytes == 8) return kind == 4 ? 3 : 2;
+    if (elem_bytes == 4) return (kind == 4 || kind == 2) ? 0 : 4;
+    return 0;
+}
+
+// Dynamic LDS per block that leaves room for the wanted number of resident
+// waves per SIMD with blocks of the given size on a CU (160 KiB of LDS, at
+// most 64 KiB per block, so at least two blocks). The size sits half a
+// block's share below the limit, so the count holds whatever the allocation
+// granularity. The kernels do not use it: it only caps residency.
+inline uint32_t residency_lds(int waves_per_simd, int block)
+{
+    if (waves_per_simd <= 0) return 0;
+    const int b = (waves_per_simd * 256) / (block < 64 ? 64 : block);
+    const uint32_t blocks = (uint32_t)(b < 2 ? 2 : b);
+    const uint32_t v = (2u * 163840u / (2u * blocks + 1u)) / 1024u * 1024u;
+    return v < 65536u ? v : 65536u;
+}
+
 struct RelaxD {
     double omega, omega_m, omega_b, omega3, omega4;
 };

@@ -64,12 +64,20 @@ LaunchFn pick_tu(int q, int dtype)
 size_t elem_bytes(int dtype) { return dtype == LBM_F64 ? 8 : dtype == LBM_F32_SHIFTED ? 4 : 2; }
 
 // SoA stride: the cell count rounded up to 1024 elements, so that every
-// population stream starts on a fresh 2-8 KiB boundary.
+// population stream starts on a fresh 2-8 KiB boundary, plus a padding picked
+// at creation. How the 19/27 stream bases fall on the HBM channels depends on
+// the stride in a way no simple rule captures (measured, FP64 AA: a 320^3
+// cavity runs at 14.0 k MLUPS unpadded and 16.8 k with 1024 elements of
+// padding, while 256^3 is best unpadded), so large lattices time a few
+// candidates. Buffers always reserve room for the largest.
+static constexpr int64_t kStridePads[] = {0, 256, 1024, 3072};
+static constexpr int64_t kMaxStridePad = 3072;
+
 int64_t soa_stride(int64_t ntot)
 {
     const int64_t a = 1024;
     int64_t s = (ntot + a - 1) / a * a;
-    if (const char* e = std::getenv("LBM_STRIDE_PAD")) s += std::atoll(e);
+    if (const char* e = std::getenv("LBM_STRIDE_PAD")) s += std::max<int64_t>(0, std::min<int64_t>(std::atoll(e), kMaxStridePad));
     return s;
 }
 
@@ -363,7 +371,8 @@ int lbm_required_bytes(const lbm_desc* d, size_t out[3])
     const int64_t n = (int64_t)d->nx * d->ny * d->nz;
     const size_t s = elem_bytes(d->storage_dtype);
     const size_t pop = d->layout == LBM_SOA
-                           ? ((size_t)soa_stride(n) * d->lattice + 2 * (size_t)soa_halo(d->ny, d->nz)) * s
+                           ? ((size_t)(soa_stride(n) + kMaxStridePad) * d->lattice +
+                              2 * (size_t)soa_halo(d->ny, d->nz)) * s
                            : (size_t)n * d->lattice * s;
     out[0] = pop;
     out[1] = d->scheme == LBM_2POP ? pop : 0;
@@ -395,33 +404,11 @@ static int init_state(lbm_handle* h, const double* rho, const double* u)
 
 // One kernel kind over the lattice: the fast part over all cells, then, for
 // the kinds that reach neighbours, the slow part over the listed cells.
-// Resident waves per SIMD the fast step kernels are held to (0: no limit),
-// by bytes per stored value and kind. Measured on the 256^3 cavity: with FP64
-// storage every wave keeps 38 streams of 512 B in flight, and two to three
-// waves per SIMD move more bytes per second than the six the registers allow
-// (AA: 15.2 -> 16.5 k MLUPS; 2Pop: 14.2 -> 15.2 k); FP32 gains with four on
-// the kinds that touch only their own cell and 2Pop, and FP16 needs every
-// wave it can get.
-static int step_waves(int elem_bytes, int kind)
-{
-    if (elem_bytes == 8) return kind == KIND_AA_ODD ? 3 : 2;
-    if (elem_bytes == 4) return (kind == KIND_AA_ODD || kind == KIND_SWAP_STREAM) ? 0 : 4;
-    return 0;
-}
-
-// Dynamic LDS per block that leaves room for the wanted number of blocks of
-// the given size on a CU (160 KiB of LDS, at most 64 KiB per block, so at
-// least two blocks). The size sits half a block's share below the limit, so
-// the count holds whatever the allocation granularity. The kernels do not
-// use it: it only caps residency.
 static uint32_t step_lds(const lbm_handle* h, int kind)
 {
     if (h->lds_override) return kind == KIND_AA_ODD || kind == KIND_2POP || kind == KIND_SWAP_STREAM
                                     ? h->lds_neighbour : h->lds_local;
-    const int w = step_waves((int)elem_bytes(h->d.storage_dtype), kind);
-    if (w <= 0) return 0;
-    const int blocks = std::max(2, w * 256 / std::max(h->block, 64));
-    return std::min<uint32_t>(65536u, (2u * 163840u / (2u * (uint32_t)blocks + 1u)) / 1024u * 1024u);
+    return residency_lds(step_waves((int)elem_bytes(h->d.storage_dtype), kind), h->block);
 }
 
 static int run_kind(lbm_handle* h, int kind)
@@ -574,6 +561,44 @@ static int enqueue_steps_graph(lbm_handle* h, int n)
         n -= kGraphSteps;
     }
     return enqueue_steps(h, n);
+}
+
+// Time the candidate stride paddings over a few steps and keep the fastest
+// (SoA lattices of at least 2^21 cells; results do not depend on the stride).
+static int tune_stride(lbm_handle* h)
+{
+    const int64_t base = soa_stride(h->ntot);
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&b), "hipEventCreate");
+    float best = 1e30f;
+    int64_t best_s = base;
+    int rc = LBM_OK;
+    for (int64_t pad : kStridePads) {
+        h->stride = base + pad;
+        rc = init_state(h, nullptr, nullptr);
+        if (!rc) rc = enqueue_steps(h, 2);
+        if (rc) break;
+        hipError_t e = hipEventRecord(a, h->stream);
+        if (e == hipSuccess) rc = enqueue_steps(h, 4);
+        if (e == hipSuccess && !rc) e = hipEventRecord(b, h->stream);
+        if (e == hipSuccess && !rc) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess) rc = hip_fail(e, "stride trial");
+        if (rc) break;
+        if (std::getenv("LBM_VERBOSE"))
+            std::fprintf(stderr, "lbm: stride %lld (pad %lld): %.3f ms per step\n", (long long)h->stride,
+                         (long long)pad, ms / 4.0);
+        if (ms < best) {
+            best = ms;
+            best_s = h->stride;
+        }
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    h->stride = best_s;
+    return rc;
 }
 
 static int autotune(lbm_handle* h)
@@ -729,6 +754,7 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
     h->cpt = d->layout == LBM_SOA ? cells_per_thread((int)elem_bytes(d->storage_dtype)) : 1;
     if (int rc = build_tables(h)) return bail(rc, lbm_last_error());
     h->use_graph = h->ntot <= kGraphCells && !std::getenv("LBM_NO_GRAPH");
+    if (std::getenv("LBM_NO_RESIDENCY_CAP")) h->lds_override = true;  // lds_local = lds_neighbour = 0
     if (const char* e = std::getenv("LBM_STEP_LDS")) {  // "bytes" or "local,neighbour"
         unsigned a = 0, b = 0;
         const int got = std::sscanf(e, "%u,%u", &a, &b);
@@ -736,6 +762,9 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
         h->lds_local = got >= 1 ? std::min(a, 65536u) : 0;
         h->lds_neighbour = got >= 2 ? std::min(b, 65536u) : h->lds_local;
     }
+    if (d->layout == LBM_SOA && h->ntot >= (int64_t(1) << 21) && !std::getenv("LBM_STRIDE_PAD") &&
+        tune_stride(h))
+        return bail(LBM_EDEVICE, lbm_last_error());
     if (init_state(h, nullptr, nullptr)) return bail(LBM_EDEVICE, lbm_last_error());
     if (d->block_size == -1) {
         if (autotune(h) || init_state(h, nullptr, nullptr)) return bail(LBM_EDEVICE, lbm_last_error());

@@ -84,8 +84,8 @@ def test_required_bytes(hiplib, scheme, dtype, layout):
     assert hiplib.lib().lbm_required_bytes(ctypes.byref(d), out) == 0
     n = 10 * 11 * 12
     s = (8, 4, 2)[dtype]
-    if layout == 0:   # SoA: streams of `stride` cells plus a halo of padding at both ends
-        stride = (n + 1023) // 1024 * 1024
+    if layout == 0:   # SoA: streams of `stride` cells (room for the largest padding) plus a halo at both ends
+        stride = (n + 1023) // 1024 * 1024 + 3072
         halo = (11 * 12 + 12 + 1 + 255) // 256 * 256
         assert out[0] == (19 * stride + 2 * halo) * s
     else:
