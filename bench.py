@@ -88,11 +88,14 @@ def copy_ceiling_gbs(nbytes: int = 2 << 30, reps: int = 20) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def run_case(scheme, coll, dtype, steps, warmup, cav):
+def run_case(scheme, coll, dtype, steps, warmup, cav, reps=1):
+    """One handle; `reps` timed runs of `steps` steps each (the first after
+    `warmup` untimed steps); the median run is reported."""
     from paper_2010_11751_amd import lbm
     sim = lbm.Lattice(19, cav.n, scheme=scheme, collision=coll, omega=cav.omega, u_lid=cav.u_lid, dtype=dtype)
     info = sim.info()
-    ms, wall = time_steps(sim, steps, warmup)
+    runs = [time_steps(sim, steps, warmup if r == 0 else 0) for r in range(reps)]
+    ms, wall = sorted(runs)[len(runs) // 2]
     m, e = sim.invariants()
     sim.close()
     fluid = info.fluid_cells
@@ -108,6 +111,7 @@ def run_case(scheme, coll, dtype, steps, warmup, cav):
         "fluid_cells": fluid,
         "finite": bool(m == m and e == e),
         "block_size": info.block_size,
+        "runs_ms_per_step": [round(r[0], 5) for r in runs],
     }
 
 
@@ -261,35 +265,43 @@ def traffic_run(cav):
     torch.cuda.synchronize()
     del a, b
     torch.cuda.empty_cache()
-    for dtype in ("f64", "f32"):
-        sim = lbm.Lattice(19, cav.n, scheme="aa", collision="bgk", omega=cav.omega, u_lid=cav.u_lid, dtype=dtype)
+    for scheme, dtype in (("aa", "f64"), ("aa", "f32"), ("2pop", "f64"), ("swap", "f64")):
+        sim = lbm.Lattice(19, cav.n, scheme=scheme, collision="bgk", omega=cav.omega, u_lid=cav.u_lid, dtype=dtype)
         sim.step(4)
         sim.sync()
         info = sim.info()
-        print(json.dumps({"traffic_run": dtype, "fluid_cells": info.fluid_cells,
-                          "algorithmic_bytes_per_launch": info.fluid_cells * info.bytes_per_update,
-                          "copy_bytes": 2 * nbytes}), flush=True)
+        print(json.dumps({"traffic_run": f"{scheme}/{dtype}", "fluid_cells": info.fluid_cells,
+                          "algorithmic_bytes_per_update": info.bytes_per_update, "copy_bytes": 2 * nbytes}),
+              flush=True)
         sim.close()
 
 
-def cpu_baseline(cav, budget_s: float = 12.0, max_steps: int = 20):
+def cpu_baseline(cav, budget_s: float = 12.0, max_steps: int = 20, single_budget_s: float = 8.0):
     """The FP64 oracle (2Pop, BGK) on the host cores, on the same 256^3
-    cavity, timed over as many whole steps as fit in about budget_s."""
-    import numpy as np
+    cavity, timed over as many whole steps as fit in about budget_s; then the
+    same on one thread (at least one whole step, about single_budget_s)."""
     import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cfg = O.Config(q=19, nx=cav.n, ny=cav.n, nz=cav.n, model=O.BGK, omega=cav.omega, u_lid=(cav.u_lid, 0, 0))
     sim = O.Simulation(cfg, "2pop")
+    O.set_threads(threads)
     sim.step(1)  # first touch of the pages
-    n, t0 = 0, time.perf_counter()
-    while n < max_steps and (time.perf_counter() - t0) < budget_s:
-        sim.step(1)
-        n += 1
-    dt = time.perf_counter() - t0
-    mlups = cav.fluid_cells * n / dt / 1e6
+
+    def timed(budget, cap):
+        n, t0 = 0, time.perf_counter()
+        while n < cap and (n == 0 or (time.perf_counter() - t0) < budget):
+            sim.step(1)
+            n += 1
+        return n, time.perf_counter() - t0
+    n, dt = timed(budget_s, max_steps)
+    O.set_threads(1)
+    n1, dt1 = timed(single_budget_s, max_steps)
+    O.set_threads(threads)
     del sim
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{n} whole 2Pop BGK FP64 steps of the 256^3 cavity ({dt:.1f} s), OpenMP over cells"}
+    return {"value": round(cav.fluid_cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n} whole 2Pop BGK FP64 steps of the 256^3 cavity ({dt:.1f} s), OpenMP over cells",
+            "single_core": {"value": round(cav.fluid_cells * n1 / dt1 / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                            "sample": f"{n1} whole steps ({dt1:.1f} s) on one thread"}}
 
 
 def main():
@@ -297,6 +309,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--reps", type=int, default=5,
+                    help="timed runs of --steps steps for the headline and FP32 figures; the median is reported")
     ap.add_argument("--no-sweep", action="store_true", help="skip the nine FP64 scheme x collision runs and the ten-model sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-configs", action="store_true",
@@ -304,8 +318,8 @@ def main():
     ap.add_argument("--domain-sweep", action="store_true",
                     help="only the MLUPS-vs-cavity-size sweep (N = 16..400; AA vs 2Pop, BGK vs RR, FP64)")
     ap.add_argument("--traffic", action="store_true",
-                    help="short run for hardware byte counters: one 1 GiB device copy, then 4 AA BGK steps of "
-                         "the 256^3 cavity in FP64 and in FP32-shifted storage")
+                    help="short run for hardware byte counters: one 1 GiB device copy, then 4 BGK steps of "
+                         "the 256^3 cavity each for AA FP64, AA FP32-shifted, 2Pop FP64 and swap FP64")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the cavity step runs on a single MI355X; "
@@ -326,9 +340,9 @@ def main():
         domain_sweep()
         return
 
-    head = run_case("aa", "bgk", "f64", args.steps, args.warmup, cav)
+    head = run_case("aa", "bgk", "f64", args.steps, args.warmup, cav, reps=args.reps)
     print(f"# f64 aa bgk: {head['mlups']:.0f} MLUPS, {head['algorithmic_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
-    f32 = run_case("aa", "bgk", "f32", args.steps, args.warmup, cav)
+    f32 = run_case("aa", "bgk", "f32", args.steps, args.warmup, cav, reps=args.reps)
     print(f"# f32 aa bgk: {f32['mlups']:.0f} MLUPS, {f32['algorithmic_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
     sweep = []
     if not args.no_sweep:
@@ -374,6 +388,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(head["ms_per_step"], 5),
+        "repetitions": len(head["runs_ms_per_step"]),
+        "runs_ms_per_step": head["runs_ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

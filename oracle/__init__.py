@@ -94,6 +94,8 @@ def lib():
         P = ctypes.c_void_p
         cfgp = ctypes.POINTER(_Cfg)
         L.oracle_lattice.argtypes = [ctypes.c_int, P, P, P]
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
         L.oracle_neighbour_index.argtypes = [cfgp, ctypes.c_int64, ctypes.c_int]
         L.oracle_neighbour_index.restype = ctypes.c_int64
         L.oracle_flags.argtypes = [cfgp, P]
@@ -122,6 +124,11 @@ def _p(a):
 def _check(rc):
     if rc != 0:
         raise RuntimeError(f"oracle call failed with {rc}")
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (for timing)."""
+    lib().oracle_set_threads(int(n))
 
 
 def lattice(q: int):

@@ -35,6 +35,9 @@
  *                               layouts agree bit for bit, shuffled order)
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -108,6 +111,16 @@ static int make_lattice(int q, olat *L)
         L->opp[k] = k == half ? half : (k < half ? k + half + 1 : k - half - 1);
     }
     return 0;
+}
+
+/* Threads of the OpenMP loops (timing only; results do not depend on it). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 int oracle_lattice(int q, int32_t *c, double *t, int32_t *opp)
