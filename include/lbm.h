@@ -40,6 +40,18 @@
  *     the caller (macroscopic, populations, flags, invariants) wait for it.
  *   - A handle is not thread safe. Errors: negative return codes, NULL
  *     handles; lbm_last_error() gives the thread's last message.
+ *
+ * Performance switches (read at handle creation; none changes any result):
+ *   LBM_STRIDE_PAD=n        fixed SoA stride padding of n elements (0..3072)
+ *                           instead of timing the candidates (lattices of
+ *                           2^21 cells and more time 0, 256, 1024, 3072)
+ *   LBM_STEP_LDS=a[,b]      fixed dynamic LDS bytes per block of the fast step
+ *                           kernels of local / neighbour kinds, replacing the
+ *                           residency cap chosen by storage type
+ *   LBM_NO_RESIDENCY_CAP    no residency cap
+ *   LBM_NO_GRAPH            no captured step graphs for small lattices
+ *   LBM_NO_OVERLAP          edge-cell kernel on the handle's stream
+ *   LBM_VERBOSE             print the stride trials to stderr
  */
 #ifndef LBM_H
 #define LBM_H
@@ -170,7 +182,9 @@ int lbm_set_geometry(lbm_handle *h, const uint8_t *type, const double *wall_velo
 
 /* Advance n >= 0 time steps (asynchronous on the handle's stream unless the
  * invariant monitor is on). AA phase is tracked, so any n is allowed.
- * Returns LBM_ENONFINITE if the monitor finds a non-finite mass or energy. */
+ * Returns LBM_ENONFINITE if the monitor finds a non-finite mass or energy.
+ * Lattices of at most 2^20 cells (monitor off) run whole groups of 64 steps
+ * from a HIP graph captured on first use; results are the same bit for bit. */
 int lbm_step(lbm_handle *h, int n);
 
 /* Density rho[Ntot] and velocity u[3][Ntot] (FP64) of the natural state;

@@ -34,7 +34,7 @@ def sample_cells(n, count, seed):
 def check_patches(sim, q, model, omega, u_lid, cells_xyz, n, tol, omega_bulk=None):
     fl_all = sim.flags().cpu().numpy()
     lin = lambda p: (p[..., 0] * n + p[..., 1]) * n + p[..., 2]
-    patch = cells_xyz[:, None, :] + OFFS[None, :, :]          # [S, 27, 3]
+    patch = (cells_xyz[:, None, :] + OFFS[None, :, :]) % n    # [S, 27, 3], wrapping for periodic boxes
     idx = lin(patch).reshape(-1)
     f_t = sim.populations_at(idx).cpu().numpy().reshape(len(cells_xyz), 27, q)
     sim.step(1)
@@ -101,3 +101,78 @@ def test_cavity_512_d3q27_rr_fp32_sampled(lbm):
     assert abs(m - cav.fluid_cells) <= 1e-6 * cav.fluid_cells
     del sim
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("coll", ("nw4", "rm", "hm", "cm", "chm", "k"))
+def test_cavity_256_moment_space_models_sampled(lbm, coll):
+    """The moment-space models at the benchmark's size and launch
+    configuration (FP64 AA, default rates: omega3 = omega4 = 1)."""
+    cav = W.CAVITY_256
+    print(f"case: 256^3 f64 aa {coll}", flush=True)
+    sim = lbm.Lattice(19, cav.n, scheme="aa", collision=coll, omega=cav.omega, u_lid=cav.u_lid)
+    sim.step(3)
+    cells = sample_cells(cav.n, 32, 83)
+    check_patches(sim, 19, coll, cav.omega, cav.u_lid, cells, cav.n, 1e-12)
+    check_patches(sim, 19, coll, cav.omega, cav.u_lid, cells, cav.n, 1e-12)
+    del sim
+    torch.cuda.empty_cache()
+
+
+def test_cavity_320_padded_stride_sampled(lbm):
+    """A size whose SoA stride gets padded at creation (320^3 FP64 AA)."""
+    n = 320
+    print("case: 320^3 f64 aa bgk", flush=True)
+    sim = lbm.Lattice(19, n, scheme="aa", collision="bgk", omega=1.9, u_lid=0.05)
+    assert sim.info().pop_stride >= n ** 3
+    sim.step(3)
+    cells = sample_cells(n, 32, 89)
+    check_patches(sim, 19, "bgk", 1.9, 0.05, cells, n, 1e-12)
+    check_patches(sim, 19, "bgk", 1.9, 0.05, cells, n, 1e-12)
+    del sim
+    torch.cuda.empty_cache()
+
+
+def test_taylor_green_256_sampled(lbm):
+    """The periodic 256^3 Taylor-Green workload (FP64 AA, BGK): sampled
+    cells on the faces, edges and corners wrap."""
+    n = W.TGV_N
+    omega = W.omega_from_nu(W.TGV_NU)
+    print("case: taylor-green 256^3 f64 aa", flush=True)
+    sim = lbm.Lattice(19, n, scheme="aa", collision="bgk", omega=omega, geometry="periodic")
+    sim.init_equilibrium(None, torch.from_numpy(W.taylor_green_velocity(n, n, n, W.TGV_U0)))
+    sim.step(3)
+    rng = np.random.default_rng(97)
+    cells = np.vstack([rng.integers(0, n, size=(24, 3)),
+                       [[0, 0, 0], [n - 1, n - 1, n - 1], [0, n // 2, n - 1], [n - 1, 0, 17], [5, n - 1, 0]]])
+    check_patches(sim, 19, "bgk", omega, 0.0, cells, n, 1e-12)
+    check_patches(sim, 19, "bgk", omega, 0.0, cells, n, 1e-12)
+    del sim
+    torch.cuda.empty_cache()
+
+
+def test_ensemble_512_fp32_graph_sampled(lbm):
+    """The full 512-cavity ensemble (FP32-shifted TRT AA, steps replayed from
+    the captured graph as the benchmark runs it): after 201 steps, sampled
+    cavities advance one more step as the oracle's reference step does from
+    the same (decoded) populations, to FP32 rounding."""
+    members = W.ensemble(512)
+    cav = [lbm.Cavity(m.n, m.omega, m.u_lid) for m in members]
+    b = lbm.Batch(cav, scheme="aa", collision="trt", dtype="f32", use_graph=True, graph_steps=100, autotune=True)
+    b.step(201)
+    sizes = [m.n for m in members]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0, 1, 255, 511})
+    before = {j: b.populations(j).cpu().numpy() for j in pick}
+    b.step(1)
+    worst = 0.0
+    for j in pick:
+        m = members[j]
+        cfg = O.Config(q=19, nx=m.n, ny=m.n, nz=m.n, model=O.TRT, omega=m.omega, u_lid=(m.u_lid, 0.0, 0.0))
+        fl = O.flags(cfg)
+        want = O.reference_step(cfg, fl, np.ascontiguousarray(before[j]).ravel()).reshape(19, -1)
+        got = b.populations(j).cpu().numpy()
+        worst = max(worst, float(np.abs(got - want).max()))
+    print(f"ensemble: worst one-step |df| = {worst:.2e}", flush=True)
+    assert worst <= 2e-7
+    masses, _ = b.invariants()
+    assert all(np.isfinite(masses))
+    b.close()
