@@ -264,3 +264,48 @@ def test_captured_step_graphs_match_oracle(lbm, scheme, q, layout):
         sim.step(n)
         ref.step(n)
         assert max_err(sim.populations().cpu().numpy(), ref.populations()) <= TOL, n
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("q,dims,geometry", [
+    (19, (3, 3, 3), "cavity"),        # one fluid cell, every neighbour a wall
+    (27, (3, 4, 3), "cavity"),        # a line of two fluid cells
+    (19, (1, 1, 1), "periodic"),      # one cell whose neighbours are all itself
+    (27, (1, 1, 1), "periodic"),
+    (19, (7, 1, 5), "periodic"),      # one-cell-thick periodic axis
+    (19, (5, 4, 3), "channel"),       # a single fluid layer between the walls
+])
+def test_degenerate_lattices_match_oracle(lbm, scheme, q, dims, geometry):
+    nx, ny, nz = dims
+    print(f"case: degenerate q={q} {dims} {geometry} {scheme}", flush=True)
+    u0 = W.random_velocity(67, nx * ny * nz, amp=0.04).T.copy()
+    sim = lbm.Lattice(q, nx, ny, nz, scheme=scheme, collision="trt", omega=1.6, u_lid=0.05, geometry=geometry)
+    cfg = oracle_cfg(q, nx, ny, nz, "trt", 1.6, (0.05, 0, 0), geometry=geometry)
+    fl = O.flags(cfg)
+    u0[:, fl != O.FLUID] = 0.0
+    sim.init_equilibrium(None, torch.from_numpy(u0))
+    ref = O.Simulation(cfg, "ref", u=u0)
+    for n in (0, 9, 1):
+        sim.step(n)
+        ref.step(n)
+        assert max_err(sim.populations().cpu().numpy(), ref.populations()) <= TOL, n
+    m, e = sim.invariants()
+    mr, er = ref.invariants()
+    assert abs(m - mr) <= 1e-12 * max(mr, 1.0)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_lattice_without_fluid_cells(lbm, scheme):
+    """A geometry of walls only: steps change nothing, invariants are zero."""
+    n = 6
+    sim = lbm.Lattice(19, n, scheme=scheme, collision="bgk", omega=1.5, u_lid=0.05)
+    cfg = oracle_cfg(19, n, n, n, "bgk", 1.5, (0.05, 0, 0))
+    wall = np.full(n ** 3, O.WALL, np.uint8)
+    sim.set_geometry(torch.from_numpy(wall))
+    assert sim.info().fluid_cells == 0
+    before = sim.populations().cpu()
+    sim.step(5)
+    assert torch.equal(sim.populations().cpu(), before)
+    assert sim.invariants() == (0.0, 0.0)
+    rho, u = sim.macroscopic()
+    assert float(rho.abs().max()) == 0.0 and float(u.abs().max()) == 0.0
