@@ -255,6 +255,51 @@ def domain_sweep():
     print(json.dumps({"domain_sweep": rows, "dtype": "f64", "lattice": "D3Q19", "layout": "SoA"}), flush=True)
 
 
+def validation():
+    """Self-convergence of the lid-driven cavity (Sec. 3.1 validation case;
+    the spectral and experimental reference data are not available): Re 100,
+    lid 0.1, FP64 AA BGK, M = 32 / 64 / 128 fluid cells per edge (cell
+    centres of the coarse grid are midpoints of fine ones), after 20 lid
+    traversals. Centreline u_x(z) and u_z(x) through the cavity centre (the
+    four nearest cell columns averaged); differences between successive
+    grids, with the coarse values compared to pair averages of the fine."""
+    import math
+    import numpy as np
+    from paper_2010_11751_amd import lbm, workloads as W
+    re, u, tstar = 100.0, 0.1, 20.0
+    prof = {}
+    for m in (32, 64, 128):
+        n = m + 2
+        sim = lbm.Lattice(19, n, scheme="aa", collision="bgk", omega=W.omega_from_nu(u * m / re), u_lid=u)
+        steps = int(round(tstar * m / u))
+        steps += steps % 2
+        sim.step(steps)
+        _, v = sim.macroscopic()
+        v = v.cpu().numpy().reshape(3, n, n, n) / u
+        c = (m // 2, m // 2 + 1)
+        ux = np.mean([v[0, a, b, 1:n - 1] for a in c for b in c], axis=0)
+        uz = np.mean([v[2, 1:n - 1, b, d] for b in c for d in c], axis=0)
+        sim.close()
+        prof[m] = (ux, uz, steps)
+        print(f"# validation M={m}: {steps} steps, min u_x/U {ux.min():.5f}, max u_z/U {uz.max():.5f}",
+              file=sys.stderr, flush=True)
+
+    def coarsen(a):
+        return 0.5 * (a[0::2] + a[1::2])
+    out = {"workload": "D3Q19 lid-driven cavity, Re 100, u_lid 0.1, FP64 AA BGK, t = 20 M / u_lid", "grids": {}}
+    for m in (32, 64, 128):
+        ux, uz, steps = prof[m]
+        out["grids"][m] = {"steps": steps, "min_ux": round(float(ux.min()), 6), "max_uz": round(float(uz.max()), 6),
+                           "min_uz": round(float(uz.min()), 6)}
+    for key, idx in (("ux", 0), ("uz", 1)):
+        d1 = float(np.abs(prof[32][idx] - coarsen(prof[64][idx])).max())
+        d2 = float(np.abs(prof[64][idx] - coarsen(prof[128][idx])).max())
+        out[f"{key}_max_diff_32_64"] = d1
+        out[f"{key}_max_diff_64_128"] = d2
+        out[f"{key}_observed_order"] = round(math.log2(d1 / d2), 3)
+    print(json.dumps({"validation": out}), flush=True)
+
+
 def traffic_run(cav):
     import torch
     from paper_2010_11751_amd import lbm
@@ -317,6 +362,8 @@ def main():
                     help="skip the 512^3 D3Q27, Taylor-Green and ensemble workloads")
     ap.add_argument("--domain-sweep", action="store_true",
                     help="only the MLUPS-vs-cavity-size sweep (N = 16..400; AA vs 2Pop, BGK vs RR, FP64)")
+    ap.add_argument("--validation", action="store_true",
+                    help="only the cavity self-convergence study (Re 100, M = 32 / 64 / 128)")
     ap.add_argument("--traffic", action="store_true",
                     help="short run for hardware byte counters: one 1 GiB device copy, then 4 BGK steps of "
                          "the 256^3 cavity each for AA FP64, AA FP32-shifted, 2Pop FP64 and swap FP64")
@@ -338,6 +385,9 @@ def main():
         return
     if args.domain_sweep:
         domain_sweep()
+        return
+    if args.validation:
+        validation()
         return
 
     head = run_case("aa", "bgk", "f64", args.steps, args.warmup, cav, reps=args.reps)

@@ -52,6 +52,9 @@
  *   LBM_NO_GRAPH            no captured step graphs for small lattices
  *   LBM_NO_OVERLAP          edge-cell kernel on the handle's stream
  *   LBM_VERBOSE             print the stride trials to stderr
+ *   LBM_REVERSE_BLOCKS      step kernels visit the cells in reverse block and
+ *                           list order (a traversal-order check: every
+ *                           scheme is independent of it, Sec. 2.3)
  */
 #ifndef LBM_H
 #define LBM_H

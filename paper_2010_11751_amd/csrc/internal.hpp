@@ -64,6 +64,7 @@ struct Field {
     int64_t stride;        // SoA elements between populations
     uint32_t ntot;
     int nx, ny, nz;
+    int reverse;           // visit cells in reverse block / list order (traversal-order tests)
 };
 
 // Largest block of the step kernels: the moment-space models (model >= 4)

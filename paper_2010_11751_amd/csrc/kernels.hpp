@@ -437,9 +437,9 @@ __device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>
     else cell_aa_odd<Q, MODEL, ST, LAYOUT, PART>(F, p, i);
 }
 
-__device__ __forceinline__ uint32_t step_block()
+__device__ __forceinline__ uint32_t step_block(const Field& F)
 {
-    uint32_t b = blockIdx.x;
+    uint32_t b = F.reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
     if (LBM_XCD_REMAP) {
         const uint32_t per = gridDim.x / 8;
         if (b < per * 8) b = (b % 8) * per + b / 8;
@@ -462,7 +462,7 @@ __device__ __forceinline__ uint32_t step_block()
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
 __global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) LBM_STEP_ATTR k_step(Field F, RelaxD pd)
 {
-    const uint32_t i = step_block() * blockDim.x + threadIdx.x;
+    const uint32_t i = step_block(F) * blockDim.x + threadIdx.x;
     if (i >= F.ntot) return;
     cell_step<Q, MODEL, ST, LAYOUT, KIND, PART_FAST>(F, relax_of<real_t<ST>>(pd), i);
 }
@@ -542,7 +542,7 @@ __device__ __forceinline__ void group_step(const Field& F, const Relax<real_t<ST
 template <int Q, int MODEL, class ST, int KIND, int CPT>
 __global__ void __launch_bounds__(256) LBM_STEP_ATTR k_step_vec(Field F, RelaxD pd)
 {
-    const uint32_t i0 = (step_block() * blockDim.x + threadIdx.x) * CPT;
+    const uint32_t i0 = (step_block(F) * blockDim.x + threadIdx.x) * CPT;
     if (i0 + CPT > F.ntot) return;  // a ragged tail is in the near-wall list
     group_step<Q, MODEL, ST, KIND, CPT>(F, relax_of<real_t<ST>>(pd), i0);
 }
@@ -552,7 +552,7 @@ __global__ void __launch_bounds__(256) LBM_STEP_ATTR k_step_vec(Field F, RelaxD 
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
 __global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) k_step_all(Field F, RelaxD pd)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = step_block(F) * blockDim.x + threadIdx.x;
     if (i >= F.ntot) return;
     cell_step<Q, MODEL, ST, LAYOUT, KIND, PART_ALL>(F, relax_of<real_t<ST>>(pd), i);
 }
@@ -564,7 +564,7 @@ __global__ void __launch_bounds__(256) k_step_slow(Field F, RelaxD pd, const uin
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const uint32_t i = list[j];
+    const uint32_t i = list[F.reverse ? n - 1 - j : j];
     if (i >= F.ntot) return;
     cell_step<Q, MODEL, ST, LAYOUT, KIND, PART_SLOW>(F, relax_of<real_t<ST>>(pd), i);
 }

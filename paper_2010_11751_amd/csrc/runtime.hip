@@ -275,6 +275,7 @@ struct lbm_handle {
     uint32_t lds_local = 0;         //   kernels of local kinds
     uint32_t lds_neighbour = 0;     //   and of the kinds that reach neighbours
     bool custom_walls = false;      // wall terms set per cell (lbm_set_geometry)
+    bool reverse_blocks = false;    // LBM_REVERSE_BLOCKS: step kernels visit cells in reverse order
     bool use_graph = false;         // small lattice: replay captured steps
     bool fused = false;             // one kernel per kind (fast and edge parts together)
     hipStream_t cap = nullptr;      // private stream the step graph is captured on
@@ -293,6 +294,7 @@ struct lbm_handle {
         F.nx = d.nx;
         F.ny = d.ny;
         F.nz = d.nz;
+        F.reverse = reverse_blocks ? 1 : 0;
         return F;
     }
     Launch base(int op) const
@@ -754,6 +756,7 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
     h->cpt = d->layout == LBM_SOA ? cells_per_thread((int)elem_bytes(d->storage_dtype)) : 1;
     if (int rc = build_tables(h)) return bail(rc, lbm_last_error());
     h->use_graph = h->ntot <= kGraphCells && !std::getenv("LBM_NO_GRAPH");
+    h->reverse_blocks = std::getenv("LBM_REVERSE_BLOCKS") != nullptr;
     if (std::getenv("LBM_NO_RESIDENCY_CAP")) h->lds_override = true;  // lds_local = lds_neighbour = 0
     if (const char* e = std::getenv("LBM_STEP_LDS")) {  // "bytes" or "local,neighbour"
         unsigned a = 0, b = 0;
