@@ -257,6 +257,10 @@ typedef struct lbm_batch_opts {
     int autotune;         /* time candidate block sizes on first step          */
     int block_size;       /* fixed block size when autotune = 0 (0 = 256)      */
     void *stream;         /* hipStream_t; NULL = a library-owned stream        */
+    const char *autotune_cache; /* text file of tuned block sizes, one "key block"
+                             line per ensemble (key: GPU arch, scheme,
+                             collision, dtype, cavity sizes); a hit skips the
+                             trial runs, a miss appends the result; NULL: none */
 } lbm_batch_opts;
 
 /* Create count cavities (FP64 or shifted FP32/FP16, D3Q19, any scheme but

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
 #include <string>
 #include <vector>
 
@@ -234,6 +235,41 @@ int autotune_batch(lbm_batch* b)
     return build_tiles(b, best_b);
 }
 
+// Key of an ensemble in the autotune cache: GPU architecture, scheme,
+// collision, storage type, cavity count and an FNV-1a hash of the cavity sizes.
+std::string cache_key(const lbm_batch* b)
+{
+    hipDeviceProp_t prop{};
+    int dev = 0;
+    std::string arch = "gpu";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        arch = arch.substr(0, arch.find(':'));
+    }
+    uint64_t h = 1469598103934665603ull;
+    for (const lbm_cavity_desc& c : b->desc)
+        for (int v : {c.nx, c.ny, c.nz}) {
+            h ^= (uint64_t)(uint32_t)v;
+            h *= 1099511628211ull;
+        }
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s/q19/s%d/c%d/d%d/n%d/%016llx", arch.c_str(), b->scheme, b->collision, b->dtype,
+                  b->count, (unsigned long long)h);
+    return buf;
+}
+
+int cached_block(const char* path, const std::string& key)
+{
+    FILE* f = std::fopen(path, "r");
+    if (!f) return 0;
+    char k[256];
+    int blk = 0, found = 0;
+    while (std::fscanf(f, "%255s %d", k, &blk) == 2)
+        if (key == k && blk >= 64 && blk <= 1024 && blk % 64 == 0) found = blk;
+    std::fclose(f);
+    return found;
+}
+
 void free_batch(lbm_batch* b)
 {
     if (!b) return;
@@ -378,7 +414,22 @@ lbm_batch* lbm_batch_create(int count, const lbm_cavity_desc* d, int scheme, int
         return bail(0);
     }
     if (build_tiles(b, std::min(block, max_step_block(19, b->collision, 8)))) return bail(0);
-    if (b->opts.autotune && (autotune_batch(b) || init_batch_state(b))) return bail(0);
+    if (b->opts.autotune) {
+        const std::string key = b->opts.autotune_cache ? cache_key(b) : std::string();
+        const int hit = b->opts.autotune_cache ? cached_block(b->opts.autotune_cache, key) : 0;
+        if (hit && hit <= max_step_block(19, b->collision, 8)) {
+            if (build_tiles(b, hit)) return bail(0);
+        } else {
+            if (autotune_batch(b) || init_batch_state(b)) return bail(0);
+            if (b->opts.autotune_cache) {
+                if (FILE* f = std::fopen(b->opts.autotune_cache, "a")) {
+                    std::fprintf(f, "%s %d\n", key.c_str(), b->block);
+                    std::fclose(f);
+                }
+            }
+        }
+    }
+    b->opts.autotune_cache = nullptr;  // the caller's string is only read at creation
     e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         hip_fail(e, "batch initialisation");

@@ -59,7 +59,7 @@ class CavityDesc(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int), ("graph_steps", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("block_size", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("block_size", ctypes.c_int), ("stream", ctypes.c_void_p), ("autotune_cache", ctypes.c_char_p)]
 
 
 SYMBOLS = [
@@ -312,7 +312,8 @@ class Batch:
     """Ensemble of independent D3Q19 cavities advanced by one launch per step."""
 
     def __init__(self, cavities, scheme: str = "aa", collision: str = "trt", dtype: str = "f32",
-                 use_graph: bool = True, graph_steps: int = 100, autotune: bool = False, block_size: int = 0):
+                 use_graph: bool = True, graph_steps: int = 100, autotune: bool = False, block_size: int = 0,
+                 autotune_cache=None):
         arr = (CavityDesc * len(cavities))()
         self.sizes = []
         for j, c in enumerate(cavities):
@@ -320,7 +321,8 @@ class Batch:
             arr[j] = CavityDesc(n, n, n, c.omega, c.u_lid, c.trt_lambda)
             self.sizes.append(n ** 3)
         self.stream = torch.cuda.current_stream()
-        opts = BatchOpts(int(use_graph), graph_steps, int(autotune), block_size, self.stream.cuda_stream)
+        opts = BatchOpts(int(use_graph), graph_steps, int(autotune), block_size, self.stream.cuda_stream,
+                         None if autotune_cache is None else str(autotune_cache).encode())
         b = lib().lbm_batch_create(len(cavities), arr, SCHEMES[scheme], COLLISIONS[collision], DTYPES[dtype],
                                    ctypes.byref(opts))
         if not b:

@@ -87,3 +87,34 @@ def test_autotuned_batch_is_still_correct(lbm):
     ref = O.Simulation(O.Config(q=19, nx=n, ny=n, nz=n, model=O.TRT, omega=w, u_lid=(u, 0, 0)), "ref")
     ref.step(6)
     assert np.abs(b.populations(1).cpu().numpy() - ref.populations()).max() <= 1e-12
+
+
+def test_autotune_cache_round_trip(lbm, tmp_path):
+    """The first autotuned creation appends its block size under the
+    ensemble's key; the second finds it and uses it without trial runs."""
+    path = tmp_path / "tune.txt"
+    cav = [lbm.Cavity(n, w, u) for n, w, u in MEMBERS]
+    a = lbm.Batch(cav, scheme="aa", collision="trt", dtype="f32", autotune=True, autotune_cache=path)
+    blk = a.info()[2]
+    a.close()
+    lines = path.read_text().split("\n")
+    assert len([l for l in lines if l.strip()]) == 1
+    key, value = lines[0].split()
+    assert int(value) == blk and key.startswith("gfx")
+    b = lbm.Batch(cav, scheme="aa", collision="trt", dtype="f32", autotune=True, autotune_cache=path)
+    assert b.info()[2] == blk
+    b.step(4)
+    b.close()
+    assert len([l for l in path.read_text().split("\n") if l.strip()]) == 1
+
+
+@pytest.mark.parametrize("coll", ("cm", "k", "rr"))
+def test_batch_other_collisions_match_oracle(lbm, coll):
+    """The ensemble with other collision models (moment-space models at
+    omega3 = omega4 = 1, omega_bulk = omega), FP64, against the oracle."""
+    b = make_batch(lbm, "f64", coll=coll)
+    b.step(10)
+    for j, (n, w, u) in enumerate(MEMBERS):
+        ref = O.Simulation(O.Config(q=19, nx=n, ny=n, nz=n, model=O.MODELS[coll], omega=w, u_lid=(u, 0, 0)), "ref")
+        ref.step(10)
+        assert np.abs(b.populations(j).cpu().numpy() - ref.populations()).max() <= 1e-12, j
