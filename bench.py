@@ -405,14 +405,14 @@ def main():
     models = None
     if not args.no_sweep:
         models = run_collision_models(max(args.steps // 5, 20), max(args.warmup // 5, 10), cav)
-    configs = {}
+    workloads = {}
     if not args.no_configs:
-        configs["cavity_512_d3q27_rr_f32"] = run_d3q27_rr(max(args.steps // 5, 20), 10)
-        print(f"# d3q27 rr 512: {configs['cavity_512_d3q27_rr_f32']['mlups']} MLUPS", file=sys.stderr, flush=True)
-        configs["taylor_green_256"] = run_taylor_green(2000)
+        workloads["cavity_512_d3q27_rr_f32"] = run_d3q27_rr(max(args.steps // 5, 20), 10)
+        print(f"# d3q27 rr 512: {workloads['cavity_512_d3q27_rr_f32']['mlups']} MLUPS", file=sys.stderr, flush=True)
+        workloads["taylor_green_256"] = run_taylor_green(2000)
         print("# taylor-green done", file=sys.stderr, flush=True)
-        configs["ensemble_512"] = run_ensemble(1000, 100)
-        print(f"# ensemble: {configs['ensemble_512']['graph']['mlups']} MLUPS (graph)", file=sys.stderr, flush=True)
+        workloads["ensemble_512"] = run_ensemble(1000, 100)
+        print(f"# ensemble: {workloads['ensemble_512']['graph']['mlups']} MLUPS (graph)", file=sys.stderr, flush=True)
     copy_gbs = copy_ceiling_gbs()
     print(f"# copy kernel: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
 
@@ -457,7 +457,7 @@ def main():
         "copy_kernel_gbs": round(copy_gbs, 1),
         "sweep_f64": sweep,
         "collision_models": models,
-        "configs": configs,
+        "workloads": workloads,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
