@@ -14,6 +14,7 @@ sums over the populations and hold them to:
 - Taylor-Green decay at the viscosity set by omega."""
 import itertools
 import math
+import os
 
 import numpy as np
 import pytest
@@ -265,3 +266,35 @@ def test_taylor_green_2d_decay_sets_viscosity(orc, model):
     e32 = tgv2d_error(orc, model, 32)
     assert abs(e32) < 2e-2
     assert 3.6 < e16 / e32 < 4.4
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_example_sec2_6.txt")
+
+
+def worked_example_rows():
+    rows = []
+    for line in open(GOLDEN):
+        if line.strip() and not line.startswith("#"):
+            v = [int(x) for x in line.split()]
+            rows.append((v[0], tuple(v[1:4]), v[4:]))
+    return rows
+
+
+@pytest.mark.parametrize("model", ("rm", "cm", "k"))
+def test_golden_worked_example(orc, model):
+    """The printed worked example (tests/golden/worked_example_sec2_6.txt):
+    the velocity order puts (-1,0,0) at k = 0 and (1,0,0) at k = 10, and the
+    outgoing populations equal rho/2 times the printed combination of the
+    post-collision raw moments of the output."""
+    c, _, _ = orc.lattice(19)
+    moments = [(1, 0, 0), (2, 0, 0), (1, 2, 0), (1, 0, 2), (2, 2, 0), (2, 0, 2)]
+    rows = worked_example_rows()
+    assert [r[0] for r in rows] == [0, 10]
+    cfg = cfg_of(orc, 19, model, **RATES)
+    for f in W.random_populations(17, 19, 5):
+        rho, u = f.sum(), velocity(c, f)
+        fo = orc.collide(cfg, f)
+        Ms = [family_moment(c, fo, n, "raw", u) for n in moments]
+        for k, ck, coef in rows:
+            assert tuple(c[k]) == ck
+            assert abs(fo[k] - rho / 2 * sum(a * m for a, m in zip(coef, Ms))) < 1e-15
