@@ -25,11 +25,12 @@
  *                               linear families at equal rates, Maxwellian
  *                               moments of the equilibrium, fixed point,
  *                               Taylor-Green decay)
- *   RR ........................ equilibrium pinned (D3Q27 product form),
- *                               third/fourth-order recursion: parity unpinned
- *                               (the paper's RR formulas are in an absent
- *                               reference; pinned only by the invariants and
- *                               reductions above)
+ *   RR ........................ pinned (D3Q27 product-form equilibrium; the
+ *                               Hermite coefficients of the output, recovered
+ *                               by projection, follow the recursion in its
+ *                               second-derivative form at every order). The
+ *                               choice of this weighted recursive form for the
+ *                               paper's RR is a reading of an absent reference.
  *   reference step, schemes ... pinned (np.roll brute force, bounce-back
  *                               permutation, mass conservation, schemes and
  *                               layouts agree bit for bit, shuffled order)
