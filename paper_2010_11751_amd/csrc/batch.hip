@@ -144,7 +144,7 @@ int build_tiles(lbm_batch* b, int block)
         if (nt > 0xffffu) return fail(LBM_EUNSUPPORTED, "cavity too large for the tile table");
         for (uint32_t j = 0; j < nt; ++j) t.push_back(((uint32_t)c << 16) | j);
     }
-    if (b->d_tiles) hipFree(b->d_tiles);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
     b->d_tiles = nullptr;
     HIP_TRY(hipMalloc(&b->d_tiles, sizeof(uint32_t) * t.size()), "hipMalloc tiles");
     HIP_TRY(hipMemcpy(b->d_tiles, t.data(), sizeof(uint32_t) * t.size(), hipMemcpyHostToDevice), "hipMemcpy tiles");
@@ -230,8 +230,8 @@ int autotune_batch(lbm_batch* b)
             best_b = c;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return build_tiles(b, best_b);
 }
 
@@ -273,15 +273,15 @@ int cached_block(const char* path, const std::string& key)
 void free_batch(lbm_batch* b)
 {
     if (!b) return;
-    if (b->stream) hipStreamSynchronize(b->stream);
-    if (b->graph) hipGraphExecDestroy(b->graph);
-    if (b->d_cav[0]) hipFree(b->d_cav[0]);
-    if (b->d_cav[1]) hipFree(b->d_cav[1]);
-    if (b->d_tiles) hipFree(b->d_tiles);
-    if (b->pool) hipFree(b->pool);
-    if (b->flags) hipFree(b->flags);
-    if (b->partial) hipFree(b->partial);
-    if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->d_cav[0]) (void)hipFree(b->d_cav[0]);
+    if (b->d_cav[1]) (void)hipFree(b->d_cav[1]);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->pool) (void)hipFree(b->pool);
+    if (b->flags) (void)hipFree(b->flags);
+    if (b->partial) (void)hipFree(b->partial);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
 
@@ -443,7 +443,7 @@ void lbm_batch_destroy(lbm_batch* b) { free_batch(b); }
 static int capture_graph(lbm_batch* b)
 {
     if (b->graph) {
-        hipGraphExecDestroy(b->graph);
+        (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
     hipGraph_t g = nullptr;
@@ -456,7 +456,7 @@ static int capture_graph(lbm_batch* b)
     if (rc) return rc;
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     b->graph_steps = b->opts.graph_steps;
     b->graph_phase = phase0;

@@ -509,7 +509,7 @@ static constexpr int64_t kGraphCells = int64_t(1) << 20;
 static int capture_steps(lbm_handle* h)
 {
     if (h->graph) {
-        hipGraphExecDestroy(h->graph);
+        (void)hipGraphExecDestroy(h->graph);
         h->graph = nullptr;
     }
     if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking), "hipStreamCreateWithFlags");
@@ -540,11 +540,11 @@ static int capture_steps(lbm_handle* h)
     h->steps = steps0;
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     if (rc || e_end != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc ? rc : hip_fail(e_end, "hipStreamEndCapture");
     }
     e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     h->graph_phase = phase0;
     h->graph_pop = pop0;
@@ -597,8 +597,8 @@ static int tune_stride(lbm_handle* h)
             best_s = h->stride;
         }
     }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     h->stride = best_s;
     return rc;
 }
@@ -628,8 +628,8 @@ static int autotune(lbm_handle* h)
             best_b = c;
         }
     }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     h->block = best_b;
     return LBM_OK;
 }
@@ -707,14 +707,14 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
 
     auto bail = [&](int code, const std::string& msg) -> lbm_handle* {
         fail(code, msg);
-        if (h->own_pop && h->pop_alloc) hipFree(h->pop_alloc);
-        if (h->own_out && h->out_alloc) hipFree(h->out_alloc);
-        if (h->own_flags && h->flags) hipFree(h->flags);
-        if (h->partial) hipFree(h->partial);
-        if (h->slow_list) hipFree(h->slow_list);
-        if (h->fork) hipEventDestroy(h->fork);
-        if (h->join) hipEventDestroy(h->join);
-        if (h->aux) hipStreamDestroy(h->aux);
+        if (h->own_pop && h->pop_alloc) (void)hipFree(h->pop_alloc);
+        if (h->own_out && h->out_alloc) (void)hipFree(h->out_alloc);
+        if (h->own_flags && h->flags) (void)hipFree(h->flags);
+        if (h->partial) (void)hipFree(h->partial);
+        if (h->slow_list) (void)hipFree(h->slow_list);
+        if (h->fork) (void)hipEventDestroy(h->fork);
+        if (h->join) (void)hipEventDestroy(h->join);
+        if (h->aux) (void)hipStreamDestroy(h->aux);
         delete h;
         return nullptr;
     };
@@ -797,19 +797,19 @@ lbm_handle* lbm_create(int lattice, int nx, int ny, int nz, int scheme, int coll
 void lbm_destroy(lbm_handle* h)
 {
     if (!h) return;
-    if (h->stream) hipStreamSynchronize(h->stream);
-    else hipDeviceSynchronize();
-    if (h->aux) hipStreamSynchronize(h->aux);
-    if (h->graph) hipGraphExecDestroy(h->graph);
-    if (h->cap) hipStreamDestroy(h->cap);
-    if (h->own_pop && h->pop_alloc) hipFree(h->pop_alloc);
-    if (h->own_out && h->out_alloc) hipFree(h->out_alloc);
-    if (h->own_flags && h->flags) hipFree(h->flags);
-    if (h->partial) hipFree(h->partial);
-    if (h->slow_list) hipFree(h->slow_list);
-    if (h->fork) hipEventDestroy(h->fork);
-    if (h->join) hipEventDestroy(h->join);
-    if (h->aux) hipStreamDestroy(h->aux);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    if (h->aux) (void)hipStreamSynchronize(h->aux);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->own_pop && h->pop_alloc) (void)hipFree(h->pop_alloc);
+    if (h->own_out && h->out_alloc) (void)hipFree(h->out_alloc);
+    if (h->own_flags && h->flags) (void)hipFree(h->flags);
+    if (h->partial) (void)hipFree(h->partial);
+    if (h->slow_list) (void)hipFree(h->slow_list);
+    if (h->fork) (void)hipEventDestroy(h->fork);
+    if (h->join) (void)hipEventDestroy(h->join);
+    if (h->aux) (void)hipStreamDestroy(h->aux);
     delete h;
 }
 
@@ -818,7 +818,7 @@ struct Staging {
     void* dev = nullptr;
     ~Staging()
     {
-        if (dev) hipFree(dev);
+        if (dev) (void)hipFree(dev);
     }
 };
 
