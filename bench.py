@@ -88,6 +88,35 @@ def copy_ceiling_gbs(nbytes: int = 2 << 30, reps: int = 20) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def stream_copy_ceiling(cav, reps: int = 20):
+    """GB/s of the library's 19-stream FP64 copy over the 256^3 cavity's cell
+    count (19 loads then 19 stores per thread, no arithmetic): the memory
+    pattern of the AA-even and swap-collide kernels alone. Uncapped, and at
+    two and three resident waves per SIMD (the step kernels' FP64 caps)."""
+    import torch
+    from paper_2010_11751_amd import lbm
+    n = cav.cells
+    stride = (n + 1023) // 1024 * 1024
+    a = torch.zeros(19 * stride, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    out = {}
+    for label, lds in (("uncapped", 0), ("3_waves", 46080), ("2_waves", 65536)):
+        lbm.stream_copy(b, a, 19, n, stride, lds)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            lbm.stream_copy(b, a, 19, n, stride, lds)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[label] = round(2 * 19 * n * 8 / (ms * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_case(scheme, coll, dtype, steps, warmup, cav, reps=1):
     """One handle; `reps` timed runs of `steps` steps each (the first after
     `warmup` untimed steps); the median run is reported."""
@@ -415,6 +444,8 @@ def main():
         print(f"# ensemble: {workloads['ensemble_512']['graph']['mlups']} MLUPS (graph)", file=sys.stderr, flush=True)
     copy_gbs = copy_ceiling_gbs()
     print(f"# copy kernel: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    streams_gbs = stream_copy_ceiling(cav)
+    print(f"# 19-stream copy: {streams_gbs} GB/s", file=sys.stderr, flush=True)
 
     def roofline(r, key):
         achieved = r["fluid_cells"] * r["bytes_per_update"] / (r["kernel_avg_ms"] * 1e-3) / 1e9
@@ -455,6 +486,7 @@ def main():
                          "hbm_gbs": round(f32["algorithmic_gbs"], 1), "speedup_vs_f64": round(f32["mlups"] / head["mlups"], 3),
                          "roofline": roofline(f32, "aa_bgk_f32_256")},
         "copy_kernel_gbs": round(copy_gbs, 1),
+        "stream_copy_19_gbs": streams_gbs,
         "sweep_f64": sweep,
         "collision_models": models,
         "workloads": workloads,

@@ -232,6 +232,16 @@ int lbm_lattice(int lattice, int32_t *c, double *t, int32_t *opp);
  * step kernels are compared with, and calibrates hardware byte counters. */
 int lbm_device_copy(void *dst, const void *src, size_t bytes, void *stream);
 
+/* Copy of nstreams (19 or 27) FP64 streams of n values each, stream s at
+ * element offset s * stride of src and dst (device pointers, 8-byte aligned;
+ * stride >= n, n < 2^32), one value of every stream per thread: all loads of
+ * a thread issued before its stores, blocks of 256 threads asking for
+ * lds_bytes (0..65536) of unused dynamic LDS to cap residency, on `stream`.
+ * Not part of the method: the memory pattern of the local step kernels
+ * without their arithmetic, the ceiling they are compared with. */
+int lbm_stream_copy(void *dst, const void *src, int nstreams, size_t n, size_t stride, int lds_bytes,
+                    void *stream);
+
 /* Wait for all work queued on the handle's stream. */
 int lbm_sync(lbm_handle *h);
 

@@ -242,6 +242,24 @@ __global__ void __launch_bounds__(256) k_copy16(uint4* __restrict__ dst, const u
     }
 }
 
+// Copy of NS separate FP64 streams, one element of each per lane: the memory
+// pattern of the local step kernels (all loads of a cell issued, then all its
+// stores) without their arithmetic or flags.
+template <int NS>
+__global__ void __launch_bounds__(256) k_copy_streams(double* __restrict__ dst, const double* __restrict__ src,
+                                                      uint64_t stride, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) v[s] = src[s * stride + i];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) asm volatile("" : "+v"(v[s]));
+#pragma unroll
+    for (int s = 0; s < NS; ++s) dst[s * stride + i] = v[s];
+}
+
 }  // namespace
 
 // --- handle --------------------------------------------------------------------
@@ -1114,6 +1132,22 @@ int lbm_device_copy(void* dst, const void* src, size_t bytes, void* stream)
     const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_for(n, 256), 1u << 23);
     k_copy16<<<grid, 256, 0, (hipStream_t)stream>>>((uint4*)dst, (const uint4*)src, n);
     HIP_TRY(hipGetLastError(), "copy launch");
+    return LBM_OK;
+}
+
+int lbm_stream_copy(void* dst, const void* src, int nstreams, size_t n, size_t stride, int lds_bytes, void* stream)
+{
+    if (!dst || !src || (nstreams != 19 && nstreams != 27) || n == 0 || n > 0xffffffffull || stride < n ||
+        lds_bytes < 0 || lds_bytes > 65536)
+        return fail(LBM_EINVAL, "stream copy: 19 or 27 streams of 1..2^32-1 values, stride >= n, LDS 0..65536");
+    const uint32_t grid = grid_for((uint64_t)n, 256);
+    if (nstreams == 19)
+        k_copy_streams<19><<<grid, 256, (uint32_t)lds_bytes, (hipStream_t)stream>>>((double*)dst, (const double*)src,
+                                                                                     stride, (uint32_t)n);
+    else
+        k_copy_streams<27><<<grid, 256, (uint32_t)lds_bytes, (hipStream_t)stream>>>((double*)dst, (const double*)src,
+                                                                                     stride, (uint32_t)n);
+    HIP_TRY(hipGetLastError(), "stream copy launch");
     return LBM_OK;
 }
 

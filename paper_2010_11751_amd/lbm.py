@@ -67,7 +67,7 @@ SYMBOLS = [
     "lbm_init_equilibrium", "lbm_set_geometry", "lbm_step", "lbm_macroscopic", "lbm_get_populations", "lbm_get_populations_at",
     "lbm_set_populations",
     "lbm_get_flags", "lbm_invariants", "lbm_neighbor_index", "lbm_get_info", "lbm_lattice", "lbm_device_copy",
-    "lbm_sync",
+    "lbm_sync", "lbm_stream_copy",
     "lbm_last_error", "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_sequential",
     "lbm_batch_macroscopic", "lbm_batch_get_populations", "lbm_batch_invariants", "lbm_batch_info",
     "lbm_batch_sync", "lbm_batch_destroy",
@@ -108,6 +108,7 @@ def lib() -> ctypes.CDLL:
     L.lbm_lattice.argtypes = [I, P, P, P]
     L.lbm_sync.argtypes = [P]
     L.lbm_device_copy.argtypes = [P, P, ctypes.c_size_t, P]
+    L.lbm_stream_copy.argtypes = [P, P, I, ctypes.c_size_t, ctypes.c_size_t, I, P]
     L.lbm_last_error.argtypes = []
     L.lbm_last_error.restype = ctypes.c_char_p
     L.lbm_batch_create.argtypes = [I, ctypes.POINTER(CavityDesc), I, I, I, ctypes.POINTER(BatchOpts)]
@@ -143,6 +144,17 @@ def lattice(q: int):
     opp = np.zeros(q, np.int32)
     check(lib().lbm_lattice(q, c.ctypes.data, t.ctypes.data, opp.ctypes.data))
     return c, t, opp
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor, nstreams: int, n: int, stride: int, lds_bytes: int = 0) -> None:
+    """Copy nstreams FP64 streams of n values (stream s at element s * stride)
+    from src to dst with the library's multi-stream kernel on the current
+    stream (the step kernels' memory pattern without arithmetic)."""
+    for t in (dst, src):
+        if t.dtype != torch.float64 or t.numel() < (nstreams - 1) * stride + n:
+            raise ValueError("float64 tensors of at least (nstreams - 1) * stride + n values needed")
+    check(lib().lbm_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nstreams, n,
+                                stride, lds_bytes, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
 
 
 def device_copy(dst: torch.Tensor, src: torch.Tensor) -> None:

@@ -360,3 +360,19 @@ def test_divergence_is_caught_and_resume_reproduces_it(lbm):
     as_bits = lambda t: t.view(torch.int64)
     assert torch.equal(as_bits(b.populations().cpu()), as_bits(c.populations().cpu()))
     assert torch.equal(as_bits(a.populations().cpu()), as_bits(c.populations().cpu()))
+
+
+@pytest.mark.parametrize("ns", (19, 27))
+def test_stream_copy_probe(lbm, ns):
+    """The bandwidth probe copies exactly the n values of each stream."""
+    n, stride = 3001, 3072
+    src = torch.randn(ns * stride, dtype=torch.float64, device="cuda")
+    dst = torch.zeros_like(src)
+    lbm.stream_copy(dst, src, ns, n, stride, 46080)
+    torch.cuda.synchronize()
+    s, d = src.view(ns, stride).cpu(), dst.view(ns, stride).cpu()
+    assert torch.equal(d[:, :n], s[:, :n])
+    assert float(d[:, n:].abs().max()) == 0.0
+    big = torch.zeros(20 * stride, dtype=torch.float64, device="cuda")
+    with pytest.raises(lbm.LBMError):      # the library takes 19 or 27 streams only
+        lbm.stream_copy(big, big.clone(), 20, n, stride)
