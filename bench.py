@@ -391,6 +391,8 @@ def main():
                     help="skip the 512^3 D3Q27, Taylor-Green and ensemble workloads")
     ap.add_argument("--domain-sweep", action="store_true",
                     help="only the MLUPS-vs-cavity-size sweep (N = 16..400; AA vs 2Pop, BGK vs RR, FP64)")
+    ap.add_argument("--jsonl", default=None,
+                    help="also append one JSON record per measured run to this file")
     ap.add_argument("--validation", action="store_true",
                     help="only the cavity self-convergence study (Re 100, M = 32 / 64 / 128)")
     ap.add_argument("--traffic", action="store_true",
@@ -493,6 +495,51 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if args.jsonl:
+        write_records(args.jsonl, out, head, f32, copy_gbs)
+
+
+def write_records(path, out, head, f32, copy_gbs):
+    """One record per measured run: workload, scheme, collision, dtype,
+    MLUPS (fluid and all cells), algorithmic GB/s and its fraction of the HBM
+    peak and of the measured copy rate, host cores of the CPU baseline."""
+    cores = (out.get("cpu_baseline") or {}).get("cores")
+    recs = []
+    for r in (head, f32):
+        recs.append({"workload": "cavity_256", "scheme": r["scheme"], "collision": r["collision"], "dtype": r["dtype"],
+                     "layout": "soa", "mlups_fluid": round(r["mlups"], 1), "mlups_total": round(r["mlups_all_cells"], 1),
+                     "gbs_algorithmic": round(r["algorithmic_gbs"], 1)})
+    for r in out["sweep_f64"]:
+        recs.append({"workload": "cavity_256", "scheme": r["scheme"], "collision": r["collision"], "dtype": "f64",
+                     "layout": "soa", "mlups_fluid": r["mlups"], "gbs_algorithmic": r["algorithmic_gbs"]})
+    for dtype, block in (out.get("collision_models") or {}).items():
+        for r in block["runs"]:
+            recs.append({"workload": "cavity_256", "scheme": "aa", "collision": r["collision"], "dtype": dtype,
+                         "layout": "soa", "mlups_fluid": r["mlups"], "gbs_algorithmic": r["algorithmic_gbs"]})
+    w = out.get("workloads") or {}
+    if "cavity_512_d3q27_rr_f32" in w:
+        r = w["cavity_512_d3q27_rr_f32"]
+        recs.append({"workload": "cavity_512_d3q27", "scheme": "aa", "collision": "rr", "dtype": "f32",
+                     "layout": "soa", "mlups_fluid": r["mlups"], "gbs_algorithmic": r["hbm_gbs"]})
+    if "taylor_green_256" in w:
+        for dtype in ("f64", "f32", "f16"):
+            r = w["taylor_green_256"][dtype]
+            recs.append({"workload": "taylor_green_256", "scheme": "aa", "collision": "bgk", "dtype": dtype,
+                         "layout": "soa", "mlups_fluid": r["mlups"], "gbs_algorithmic": r["hbm_gbs"],
+                         "velocity_rel_l2_vs_f64": r.get("velocity_rel_l2_vs_f64")})
+    if "ensemble_512" in w:
+        for mode in ("graph", "sequential"):
+            r = w["ensemble_512"][mode]
+            recs.append({"workload": "ensemble_512", "scheme": "aa", "collision": "trt", "dtype": "f32",
+                         "layout": "soa", "mode": mode, "mlups_fluid": r["mlups"]})
+    with open(path, "a") as f:
+        for r in recs:
+            g = r.get("gbs_algorithmic")
+            if g:
+                r["pct_peak"] = round(100 * g / PEAK_HBM_GBS, 2)
+                r["pct_copy"] = round(100 * g / copy_gbs, 2)
+            r["host_cores"] = cores
+            f.write(json.dumps(r) + "\n")
 
 
 if __name__ == "__main__":
