@@ -91,23 +91,27 @@ def copy_ceiling_gbs(nbytes: int = 2 << 30, reps: int = 20) -> float:
 def stream_copy_ceiling(cav, reps: int = 20):
     """GB/s of the library's 19-stream FP64 copy over the 256^3 cavity's cell
     count (19 loads then 19 stores per thread, no arithmetic): the memory
-    pattern of the AA-even and swap-collide kernels alone. Uncapped, and at
-    two and three resident waves per SIMD (the step kernels' FP64 caps)."""
+    pattern of the AA-even and swap-collide kernels alone, uncapped and at two
+    and three resident waves per SIMD (the step kernels' FP64 caps), and the
+    AA-odd pattern (stream s read at i - d_s, written at i + d_s) at several."""
     import torch
     from paper_2010_11751_amd import lbm
     n = cav.cells
     stride = (n + 1023) // 1024 * 1024
-    a = torch.zeros(19 * stride, dtype=torch.float64, device="cuda")
+    halo = cav.n * cav.n + cav.n + 1
+    a = torch.zeros(19 * stride + 2 * halo, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     out = {}
-    for label, lds in (("uncapped", 0), ("3_waves", 46080), ("2_waves", 65536)):
-        lbm.stream_copy(b, a, 19, n, stride, lds)
+    for label, lds, shift in (("uncapped", 0, None), ("3_waves", 46080, None), ("2_waves", 65536, None),
+                              ("odd_pattern_uncapped", 0, (cav.n, cav.n)), ("odd_pattern_4_waves", 35840, (cav.n, cav.n)),
+                              ("odd_pattern_3_waves", 46080, (cav.n, cav.n)), ("odd_pattern_2_waves", 65536, (cav.n, cav.n))):
+        lbm.stream_copy(b, a, 19, n, stride, lds, shift=shift)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            lbm.stream_copy(b, a, 19, n, stride, lds)
+            lbm.stream_copy(b, a, 19, n, stride, lds, shift=shift)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps

@@ -237,10 +237,14 @@ int lbm_device_copy(void *dst, const void *src, size_t bytes, void *stream);
  * stride >= n, n < 2^32), one value of every stream per thread: all loads of
  * a thread issued before its stores, blocks of 256 threads asking for
  * lds_bytes (0..65536) of unused dynamic LDS to cap residency, on `stream`.
- * Not part of the method: the memory pattern of the local step kernels
- * without their arithmetic, the ceiling they are compared with. */
-int lbm_stream_copy(void *dst, const void *src, int nstreams, size_t n, size_t stride, int lds_bytes,
-                    void *stream);
+ * With ny = nz = 0 value i of every stream is copied in place; with both >= 1
+ * stream s is read at i - d_s and written at i + d_s, d_s = (c_sx ny + c_sy)
+ * nz + c_sz the offset of lattice velocity s (the AA odd step's pattern), and
+ * both buffers must extend ny*nz + nz + 1 values before element 0 and after
+ * the last stream. Not part of the method: the memory patterns of the step
+ * kernels without their arithmetic, the ceilings they are compared with. */
+int lbm_stream_copy(void *dst, const void *src, int nstreams, size_t n, size_t stride, int lds_bytes, int ny,
+                    int nz, void *stream);
 
 /* Wait for all work queued on the handle's stream. */
 int lbm_sync(lbm_handle *h);

@@ -244,20 +244,29 @@ __global__ void __launch_bounds__(256) k_copy16(uint4* __restrict__ dst, const u
 
 // Copy of NS separate FP64 streams, one element of each per lane: the memory
 // pattern of the local step kernels (all loads of a cell issued, then all its
-// stores) without their arithmetic or flags.
+// stores) without their arithmetic or flags. With shifts, stream s is read at
+// i - d_s and written at i + d_s, d_s the offset of the lattice velocity c_s
+// (the AA odd step's pattern).
 template <int NS>
 __global__ void __launch_bounds__(256) k_copy_streams(double* __restrict__ dst, const double* __restrict__ src,
-                                                      uint64_t stride, uint32_t n)
+                                                      uint64_t stride, uint32_t n, int ny, int nz)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double v[NS];
+    const bool shifted = nz > 0;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) v[s] = src[s * stride + i];
+    for (int s = 0; s < NS; ++s) {
+        const int64_t d = shifted ? ((int64_t)L<NS>::cx(s) * ny + L<NS>::cy(s)) * nz + L<NS>::cz(s) : 0;
+        v[s] = src[(int64_t)(s * stride + i) - d];
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) asm volatile("" : "+v"(v[s]));
 #pragma unroll
-    for (int s = 0; s < NS; ++s) dst[s * stride + i] = v[s];
+    for (int s = 0; s < NS; ++s) {
+        const int64_t d = shifted ? ((int64_t)L<NS>::cx(s) * ny + L<NS>::cy(s)) * nz + L<NS>::cz(s) : 0;
+        dst[(int64_t)(s * stride + i) + d] = v[s];
+    }
 }
 
 }  // namespace
@@ -1135,18 +1144,21 @@ int lbm_device_copy(void* dst, const void* src, size_t bytes, void* stream)
     return LBM_OK;
 }
 
-int lbm_stream_copy(void* dst, const void* src, int nstreams, size_t n, size_t stride, int lds_bytes, void* stream)
+int lbm_stream_copy(void* dst, const void* src, int nstreams, size_t n, size_t stride, int lds_bytes, int ny,
+                    int nz, void* stream)
 {
     if (!dst || !src || (nstreams != 19 && nstreams != 27) || n == 0 || n > 0xffffffffull || stride < n ||
-        lds_bytes < 0 || lds_bytes > 65536)
-        return fail(LBM_EINVAL, "stream copy: 19 or 27 streams of 1..2^32-1 values, stride >= n, LDS 0..65536");
+        lds_bytes < 0 || lds_bytes > 65536 || ny < 0 || nz < 0 || (nz > 0 && ny < 1) ||
+        (int64_t)ny * nz > (1ll << 30))
+        return fail(LBM_EINVAL, "stream copy: 19 or 27 streams of 1..2^32-1 values, stride >= n, LDS 0..65536, "
+                                "ny = nz = 0 or both >= 1");
     const uint32_t grid = grid_for((uint64_t)n, 256);
     if (nstreams == 19)
         k_copy_streams<19><<<grid, 256, (uint32_t)lds_bytes, (hipStream_t)stream>>>((double*)dst, (const double*)src,
-                                                                                     stride, (uint32_t)n);
+                                                                                     stride, (uint32_t)n, ny, nz);
     else
         k_copy_streams<27><<<grid, 256, (uint32_t)lds_bytes, (hipStream_t)stream>>>((double*)dst, (const double*)src,
-                                                                                     stride, (uint32_t)n);
+                                                                                     stride, (uint32_t)n, ny, nz);
     HIP_TRY(hipGetLastError(), "stream copy launch");
     return LBM_OK;
 }

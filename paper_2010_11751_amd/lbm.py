@@ -108,7 +108,7 @@ def lib() -> ctypes.CDLL:
     L.lbm_lattice.argtypes = [I, P, P, P]
     L.lbm_sync.argtypes = [P]
     L.lbm_device_copy.argtypes = [P, P, ctypes.c_size_t, P]
-    L.lbm_stream_copy.argtypes = [P, P, I, ctypes.c_size_t, ctypes.c_size_t, I, P]
+    L.lbm_stream_copy.argtypes = [P, P, I, ctypes.c_size_t, ctypes.c_size_t, I, I, I, P]
     L.lbm_last_error.argtypes = []
     L.lbm_last_error.restype = ctypes.c_char_p
     L.lbm_batch_create.argtypes = [I, ctypes.POINTER(CavityDesc), I, I, I, ctypes.POINTER(BatchOpts)]
@@ -146,15 +146,23 @@ def lattice(q: int):
     return c, t, opp
 
 
-def stream_copy(dst: torch.Tensor, src: torch.Tensor, nstreams: int, n: int, stride: int, lds_bytes: int = 0) -> None:
+def stream_copy(dst: torch.Tensor, src: torch.Tensor, nstreams: int, n: int, stride: int, lds_bytes: int = 0,
+                shift=None) -> None:
     """Copy nstreams FP64 streams of n values (stream s at element s * stride)
     from src to dst with the library's multi-stream kernel on the current
-    stream (the step kernels' memory pattern without arithmetic)."""
+    stream (the step kernels' memory pattern without arithmetic). With
+    shift = (ny, nz) stream s is read at i - d_s and written at i + d_s (the AA
+    odd step's pattern); the tensors then start ny*nz + nz + 1 values before
+    element 0 and end as far after the last stream."""
+    ny, nz = (0, 0) if shift is None else shift
+    halo = ny * nz + nz + 1 if shift is not None else 0
     for t in (dst, src):
-        if t.dtype != torch.float64 or t.numel() < (nstreams - 1) * stride + n:
-            raise ValueError("float64 tensors of at least (nstreams - 1) * stride + n values needed")
-    check(lib().lbm_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nstreams, n,
-                                stride, lds_bytes, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        if t.dtype != torch.float64 or t.numel() < (nstreams - 1) * stride + n + 2 * halo:
+            raise ValueError("float64 tensors of at least (nstreams - 1) * stride + n (+ 2 halo) values needed")
+    off = halo * 8
+    check(lib().lbm_stream_copy(ctypes.c_void_p(dst.data_ptr() + off), ctypes.c_void_p(src.data_ptr() + off),
+                                nstreams, n, stride, lds_bytes, ny, nz,
+                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
 
 
 def device_copy(dst: torch.Tensor, src: torch.Tensor) -> None:

@@ -376,3 +376,15 @@ def test_stream_copy_probe(lbm, ns):
     big = torch.zeros(20 * stride, dtype=torch.float64, device="cuda")
     with pytest.raises(lbm.LBMError):      # the library takes 19 or 27 streams only
         lbm.stream_copy(big, big.clone(), 20, n, stride)
+    # shifted (AA odd) pattern: stream s read at i - d_s, written at i + d_s
+    ny, nz = 4, 5
+    halo = ny * nz + nz + 1
+    src = torch.randn(ns * stride + 2 * halo, dtype=torch.float64, device="cuda")
+    dst = torch.zeros_like(src)
+    lbm.stream_copy(dst, src, ns, n, stride, 0, shift=(ny, nz))
+    c, _, _ = O.lattice(ns)
+    s_, d_ = src.cpu().numpy(), dst.cpu().numpy()
+    i = np.arange(n)
+    for k in range(ns):
+        off = (int(c[k, 0]) * ny + int(c[k, 1])) * nz + int(c[k, 2])
+        assert np.array_equal(d_[halo + k * stride + i + off], s_[halo + k * stride + i - off]), k
