@@ -69,10 +69,17 @@ struct Field {
 
 // Largest block of the step kernels: the moment-space models (model >= 4)
 // and D3Q27 in FP64 need more registers per lane than 1024-thread blocks
-// leave them (128 VGPRs).
+// leave them (128 VGPRs). TRT and RR (models 1 and 3), which hold each
+// population beside its opposite, spill at 128 VGPRs in the AA odd step in
+// FP64 and on D3Q27; 512-thread blocks (256 VGPRs) remove the spills, which
+// pays in FP64 (held to three waves per SIMD anyway) and in FP16 on D3Q27
+// (+4 % on the 256^3 and 384^3 cavities). D3Q27 in FP32 keeps four waves
+// with a few spilled registers: three waves without measured 2 % slower.
 constexpr int max_step_block(int q, int model, int elem_bytes)
 {
-    return (model >= 4 || (q == 27 && elem_bytes == 8)) ? 256 : 1024;
+    if (model >= 4 || (q == 27 && elem_bytes == 8)) return 256;
+    if ((model == 1 || model == 3) && (elem_bytes == 8 || (q == 27 && elem_bytes == 2))) return 512;
+    return 1024;
 }
 
 // Resident waves per SIMD the fast step kernels are held to (0: no limit),
