@@ -82,6 +82,17 @@ constexpr int max_step_block(int q, int model, int elem_bytes)
     return 1024;
 }
 
+// Waves per SIMD the registers of a fast step kernel must leave room for.
+// FP64 kernels run at the two (AA odd: three) waves the residency cap
+// below allows; the central-moment models on D3Q27 (AA odd) and D3Q19
+// (CM, CHM, cumulant, AA odd) otherwise take one register too many for
+// them (302 and 172-174 registers).
+constexpr int min_step_waves(int q, int elem_bytes, int kind)
+{
+    if (elem_bytes != 8) return 1;
+    return (kind == 4 && q == 19) ? 3 : 2;
+}
+
 // Resident waves per SIMD the fast step kernels are held to (0: no limit),
 // by bytes per stored value and kind. Measured on the 256^3 cavity: with FP64
 // storage every wave keeps 38 streams of 512 B in flight, and two to three

@@ -447,20 +447,14 @@ __device__ __forceinline__ uint32_t step_block(const Field& F)
     return b;
 }
 
-// Minimum waves per SIMD the compiler must fit the fast step kernels into
-// (0: compiler's choice).
-#ifndef LBM_WAVES_PER_EU
-#define LBM_WAVES_PER_EU 0
-#endif
-#if LBM_WAVES_PER_EU > 0
-#define LBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
-#else
-#define LBM_STEP_ATTR
-#endif
+// Register budget of the fast step kernels: room for min_step_waves waves
+// per SIMD.
+#define LBM_STEP_ATTR(Q, ST, KIND) \
+    __attribute__((amdgpu_waves_per_eu(min_step_waves(Q, (int)sizeof(typename ST::T), KIND))))
 
 // Fast part over every cell of the lattice.
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
-__global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) LBM_STEP_ATTR k_step(Field F, RelaxD pd)
+__global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) LBM_STEP_ATTR(Q, ST, KIND) k_step(Field F, RelaxD pd)
 {
     const uint32_t i = step_block(F) * blockDim.x + threadIdx.x;
     if (i >= F.ntot) return;
@@ -540,7 +534,7 @@ __device__ __forceinline__ void group_step(const Field& F, const Relax<real_t<ST
 }
 
 template <int Q, int MODEL, class ST, int KIND, int CPT>
-__global__ void __launch_bounds__(256) LBM_STEP_ATTR k_step_vec(Field F, RelaxD pd)
+__global__ void __launch_bounds__(256) LBM_STEP_ATTR(Q, ST, KIND) k_step_vec(Field F, RelaxD pd)
 {
     const uint32_t i0 = (step_block(F) * blockDim.x + threadIdx.x) * CPT;
     if (i0 + CPT > F.ntot) return;  // a ragged tail is in the near-wall list
@@ -550,7 +544,7 @@ __global__ void __launch_bounds__(256) LBM_STEP_ATTR k_step_vec(Field F, RelaxD 
 // Fast and slow parts in one pass over every cell (one launch per step, as
 // the per-cavity reference path of the batched ensemble uses).
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
-__global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) k_step_all(Field F, RelaxD pd)
+__global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) LBM_STEP_ATTR(Q, ST, KIND) k_step_all(Field F, RelaxD pd)
 {
     const uint32_t i = step_block(F) * blockDim.x + threadIdx.x;
     if (i >= F.ntot) return;
