@@ -343,7 +343,7 @@ def traffic_run(cav):
     torch.cuda.synchronize()
     del a, b
     torch.cuda.empty_cache()
-    for scheme, dtype in (("aa", "f64"), ("aa", "f32"), ("2pop", "f64"), ("swap", "f64")):
+    for scheme, dtype in (("aa", "f64"), ("aa", "f32"), ("2pop", "f64"), ("swap", "f64"), ("2pop_pull", "f64")):
         sim = lbm.Lattice(19, cav.n, scheme=scheme, collision="bgk", omega=cav.omega, u_lid=cav.u_lid, dtype=dtype)
         sim.step(4)
         sim.sync()
@@ -431,12 +431,21 @@ def main():
     print(f"# f32 aa bgk: {f32['mlups']:.0f} MLUPS, {f32['algorithmic_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
     sweep = []
     if not args.no_sweep:
-        for scheme in ("2pop", "swap", "aa"):
+        for scheme in ("2pop", "swap", "aa", "2pop_pull"):
             for coll in ("bgk", "trt", "reg"):
                 r = run_case(scheme, coll, "f64", max(args.steps // 5, 20), max(args.warmup // 5, 10), cav)
                 sweep.append({k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()
                               if k in ("scheme", "collision", "mlups", "algorithmic_gbs", "ms_per_step")})
                 print(f"# sweep {scheme} {coll}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    shifted_schemes = []
+    if not args.no_sweep:
+        for dtype in ("f32", "f16"):
+            for scheme in ("2pop", "aa", "2pop_pull"):
+                r = run_case(scheme, "bgk", dtype, max(args.steps // 5, 20), max(args.warmup // 5, 10), cav)
+                shifted_schemes.append({k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()
+                                        if k in ("scheme", "collision", "dtype", "mlups", "algorithmic_gbs",
+                                                 "ms_per_step")})
+                print(f"# {dtype} {scheme} bgk: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     models = None
     if not args.no_sweep:
         models = run_collision_models(max(args.steps // 5, 20), max(args.warmup // 5, 10), cav)
@@ -494,6 +503,7 @@ def main():
         "copy_kernel_gbs": round(copy_gbs, 1),
         "stream_copy_19_gbs": streams_gbs,
         "sweep_f64": sweep,
+        "schemes_shifted_bgk": shifted_schemes,
         "collision_models": models,
         "workloads": workloads,
         "cpu_baseline": cpu,
@@ -515,6 +525,9 @@ def write_records(path, out, head, f32, copy_gbs):
                      "gbs_algorithmic": round(r["algorithmic_gbs"], 1)})
     for r in out["sweep_f64"]:
         recs.append({"workload": "cavity_256", "scheme": r["scheme"], "collision": r["collision"], "dtype": "f64",
+                     "layout": "soa", "mlups_fluid": r["mlups"], "gbs_algorithmic": r["algorithmic_gbs"]})
+    for r in out.get("schemes_shifted_bgk") or []:
+        recs.append({"workload": "cavity_256", "scheme": r["scheme"], "collision": r["collision"], "dtype": r["dtype"],
                      "layout": "soa", "mlups_fluid": r["mlups"], "gbs_algorithmic": r["algorithmic_gbs"]})
     for dtype, block in (out.get("collision_models") or {}).items():
         for r in block["runs"]:

@@ -11,6 +11,7 @@
  *     f_kbar(x, t+1) = f_out_k(x, t) - 6 t_k rho_w c_k . u_w, rho_w = 1,
  *     wall cells storing the precomputed term        (Eqs. storage1, storage2)
  *   - memory-access schemes 2Pop / swap / AA        (Sec. 2.3, Table 1)
+ *     and 2Pop in pull form (below)
  *   - layouts SoA pop[k][N] and AoS pop[N][Q]       (Sec. 2.3)
  *   - collision models BGK, TRT, regularized, recursive regularized, and the
  *     moment-space models of Sec. 2.2 (BGK with the non-weighted fourth-order
@@ -74,7 +75,17 @@ enum lbm_status {
     LBM_ENONFINITE = -4,   /* invariant monitor found NaN/Inf                 */
     LBM_EUNSUPPORTED = -5  /* valid but unsupported combination               */
 };
-enum lbm_scheme { LBM_2POP = 0, LBM_SWAP = 1, LBM_AA = 2 };
+/* LBM_2POP, LBM_SWAP and LBM_AA are the three schemes of Sec. 2.3 (Table 1;
+ * 2Pop pushes each f_out_k to its neighbour). LBM_2POP_PULL is the
+ * two-population scheme in pull form, not in the paper: between steps the
+ * arrays hold post-collision values in slot kbar, as the AA pattern does after
+ * an even step, and a step gathers f_k(x) from pop_kbar(x - c_k) (or
+ * pop_k(x) + pop_kbar(x - c_k) across a wall), collides and stores
+ * out_kbar(x) <- f_out_k at the cell's own index. The first step from a
+ * pre-collision state (creation, lbm_init_equilibrium, lbm_set_populations)
+ * is an AA even step. Its shifted accesses are reads, not writes. Results are
+ * identical to the other schemes; read-outs apply the pending gather. */
+enum lbm_scheme { LBM_2POP = 0, LBM_SWAP = 1, LBM_AA = 2, LBM_2POP_PULL = 3 };
 /* BGK: BGK with the weighted second-order equilibrium (BGK-W2). TRT: two
  * relaxation times (Lambda). REG / RR: regularized and recursive regularized
  * (weighted Hermite). The moment-space models use the non-weighted basis of
@@ -135,7 +146,8 @@ typedef struct lbm_info {
     int64_t steps_done;       /* steps advanced since creation / last set      */
     int64_t first_nonfinite;  /* step at which the monitor tripped, else -1    */
     int64_t bytes_per_update; /* algorithmic HBM bytes per fluid-cell update    */
-    int aa_phase;             /* AA: 1 if the next step is odd                 */
+    int aa_phase;             /* AA: 1 if the next step is odd; 2Pop pull: 1
+                                 once the state is post-collision            */
     int block_size;           /* block size the step kernels use               */
 } lbm_info;
 
@@ -144,7 +156,7 @@ typedef struct lbm_info {
 void lbm_desc_default(lbm_desc *d);
 
 /* Bytes of the population array(s) and flag array the description needs:
- * out[0] = pop, out[1] = out (0 unless 2Pop), out[2] = flags. Caller buffers
+ * out[0] = pop, out[1] = out (0 unless 2Pop or 2Pop pull), out[2] = flags. Caller buffers
  * must be at least this large and 256-byte aligned. Returns a status. */
 int lbm_required_bytes(const lbm_desc *d, size_t out[3]);
 
@@ -277,8 +289,8 @@ typedef struct lbm_batch_opts {
                              trial runs, a miss appends the result; NULL: none */
 } lbm_batch_opts;
 
-/* Create count cavities (FP64 or shifted FP32/FP16, D3Q19, any scheme but
- * swap, any collision; omega_bulk = omega and, for the moment-space models,
+/* Create count cavities (FP64 or shifted FP32/FP16, D3Q19, 2Pop or AA
+ * (swap and 2Pop pull: LBM_EUNSUPPORTED), any collision; omega_bulk = omega and, for the moment-space models,
  * omega3 = omega4 = 1). opts may be NULL. Initial state: rho = 1, u = 0. */
 lbm_batch *lbm_batch_create(int count, const lbm_cavity_desc *d, int scheme, int collision,
                             int storage_dtype, const lbm_batch_opts *opts);

@@ -108,6 +108,7 @@ def lib():
         L.oracle_reference_step.argtypes = [cfgp, P, P, P]
         L.oracle_reference_cells.argtypes = [cfgp, P, P, P, ctypes.c_int64, P]
         L.oracle_2pop_step.argtypes = [cfgp, P, P, P, P]
+        L.oracle_pull_step.argtypes = [cfgp, P, P, P, P]
         L.oracle_swap_step.argtypes = [cfgp, P, P, P]
         L.oracle_aa_step.argtypes = [cfgp, P, P, ctypes.c_int, P]
         L.oracle_aa_natural.argtypes = [cfgp, P, P, P]
@@ -197,6 +198,10 @@ def twopop_step(cfg: Config, fl, pop, out, order=None) -> None:
     _check(lib().oracle_2pop_step(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), _p(out), _p(order)))
 
 
+def pull_step(cfg: Config, fl, pop, out, order=None) -> None:
+    _check(lib().oracle_pull_step(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), _p(out), _p(order)))
+
+
 def swap_step(cfg: Config, fl, pop, order=None) -> None:
     _check(lib().oracle_swap_step(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), _p(order)))
 
@@ -234,8 +239,10 @@ def to_soa(cfg: Config, pop) -> np.ndarray:
 
 
 class Simulation:
-    """Runs the oracle with one of the three schemes of Table 1 and reads back
-    the natural pre-collision populations f[k][Ntot] at whole steps."""
+    """Runs the oracle with one of the three schemes of Table 1, or the
+    two-population scheme in pull form ("2pop_pull": an AA even step first,
+    then pull steps between two arrays), and reads back the natural
+    pre-collision populations f[k][Ntot] at whole steps."""
 
     def __init__(self, cfg: Config, scheme: str = "2pop", rho=None, u=None, order=None, cell_types=None,
                  wall_u=None, wall_rho=None):
@@ -245,7 +252,7 @@ class Simulation:
         self.cfg, self.scheme, self.order = cfg, scheme, order
         self.flags = flags(cfg) if cell_types is None else np.ascontiguousarray(cell_types, dtype=np.uint8).copy()
         self.pop = init_state(cfg, self.flags, rho, u, wall_u, wall_rho)
-        self.out = self.pop.copy() if scheme == "2pop" else None
+        self.out = self.pop.copy() if scheme in ("2pop", "2pop_pull") else None
         self.t = 0
 
     def step(self, n: int = 1) -> None:
@@ -259,13 +266,19 @@ class Simulation:
                 swap_step(self.cfg, self.flags, self.pop, self.order)
             elif self.scheme == "aa":
                 aa_step(self.cfg, self.flags, self.pop, self.t % 2 == 1, self.order)
+            elif self.scheme == "2pop_pull":
+                if self.t == 0:
+                    aa_step(self.cfg, self.flags, self.pop, False, self.order)
+                else:
+                    pull_step(self.cfg, self.flags, self.pop, self.out, self.order)
+                    self.pop, self.out = self.out, self.pop
             else:
                 raise ValueError(self.scheme)
             self.t += 1
 
     def natural(self) -> np.ndarray:
         """Pre-collision populations in the configured layout."""
-        if self.scheme == "aa" and self.t % 2 == 1:
+        if (self.scheme == "aa" and self.t % 2 == 1) or (self.scheme == "2pop_pull" and self.t > 0):
             return aa_natural(self.cfg, self.flags, self.pop)
         return self.pop.copy()
 

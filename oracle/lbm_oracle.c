@@ -887,6 +887,38 @@ int oracle_aa_step(const ocfg *g, const uint8_t *flags, double *pop, int odd, co
     return 0;
 }
 
+/* Double-population scheme in pull form (Table 1's 2Pop pushes instead).
+ * Between steps both arrays hold post-collision values at opposite slots,
+ * as the AA array after an even step; the entry step from a pre-collision
+ * state is the AA even step. A step gathers f_k(x) from pop_kbar(x - c_k),
+ * or pop_k(x) + pop_kbar(x - c_k) across a wall, collides, and stores f_out_k
+ * at out_kbar(x); the caller then exchanges the arrays. Both arrays hold the
+ * wall terms in wall cells. */
+int oracle_pull_step(const ocfg *g, const uint8_t *flags, const double *pop, double *out,
+                     const int64_t *order)
+{
+    olat L;
+    int64_t j, n = ntot(g);
+    if (make_lattice(g->q, &L)) return -1;
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < n; ++j) {
+        int64_t i = pick(order, j);
+        double tmp[27], fo[27];
+        int k;
+        if (flags[i] != O_FLUID) continue;
+        for (k = 0; k < L.q; ++k) {
+            int64_t s;
+            if (k == L.rest) { tmp[k] = pop[at(g, i, k)]; continue; }
+            s = neighbour(g, i, L.c[k], -1);
+            if (flags[s] == O_FLUID) tmp[k] = pop[at(g, s, L.opp[k])];
+            else tmp[k] = pop[at(g, i, k)] + pop[at(g, s, L.opp[k])];
+        }
+        collide(&L, g, tmp, fo);
+        for (k = 0; k < L.q; ++k) out[at(g, i, L.opp[k])] = fo[k];
+    }
+    return 0;
+}
+
 /* Natural pre-collision populations of an AA array left by an even step:
  * the odd-step pull without the collision. Wall cells copy their terms. */
 int oracle_aa_natural(const ocfg *g, const uint8_t *flags, const double *pop, double *f)

@@ -297,7 +297,7 @@ lbm_batch* lbm_batch_create(int count, const lbm_cavity_desc* d, int scheme, int
         return nullptr;
     }
     if (scheme != LBM_2POP && scheme != LBM_AA) {
-        fail(scheme == LBM_SWAP ? LBM_EUNSUPPORTED : LBM_EINVAL, "batch schemes: 2Pop or AA");
+        fail(scheme == LBM_SWAP || scheme == LBM_2POP_PULL ? LBM_EUNSUPPORTED : LBM_EINVAL, "batch schemes: 2Pop or AA");
         return nullptr;
     }
     if (collision < LBM_BGK || collision > LBM_K || storage_dtype < LBM_F64 || storage_dtype > LBM_F16_SHIFTED) {

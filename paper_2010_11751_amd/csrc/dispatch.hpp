@@ -29,6 +29,7 @@ hipError_t launch_step_kind(const Launch& L, hipStream_t s)
     case KIND_SWAP_STREAM: k_step<Q, BGK, ST, LAYOUT, KIND_SWAP_STREAM><<<g, b, lds, s>>>(L.F, L.relax); break;
     case KIND_AA_EVEN: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_EVEN><<<g, b, lds, s>>>(L.F, L.relax); break;
     case KIND_AA_ODD: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, lds, s>>>(L.F, L.relax); break;
+    case KIND_PULL: k_step<Q, MODEL, ST, LAYOUT, KIND_PULL><<<g, b, lds, s>>>(L.F, L.relax); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -42,6 +43,7 @@ hipError_t launch_all_kind(const Launch& L, hipStream_t s)
     case KIND_2POP: k_step_all<Q, MODEL, ST, LAYOUT, KIND_2POP><<<g, b, 0, s>>>(L.F, L.relax); break;
     case KIND_AA_EVEN: k_step_all<Q, MODEL, ST, LAYOUT, KIND_AA_EVEN><<<g, b, 0, s>>>(L.F, L.relax); break;
     case KIND_AA_ODD: k_step_all<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, 0, s>>>(L.F, L.relax); break;
+    case KIND_PULL: k_step_all<Q, MODEL, ST, LAYOUT, KIND_PULL><<<g, b, 0, s>>>(L.F, L.relax); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -58,6 +60,7 @@ hipError_t launch_slow_kind(const Launch& L, hipStream_t s)
         break;
     case KIND_AA_ODD: k_step_slow<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, 0, s>>>(L.F, L.relax, L.slow_list, L.n_slow); break;
     case KIND_AA_EVEN: k_step_slow<Q, MODEL, ST, LAYOUT, KIND_AA_EVEN><<<g, b, 0, s>>>(L.F, L.relax, L.slow_list, L.n_slow); break;
+    case KIND_PULL: k_step_slow<Q, MODEL, ST, LAYOUT, KIND_PULL><<<g, b, 0, s>>>(L.F, L.relax, L.slow_list, L.n_slow); break;
     case KIND_SWAP_COLLIDE:
         k_step_slow<Q, MODEL, ST, LAYOUT, KIND_SWAP_COLLIDE><<<g, b, 0, s>>>(L.F, L.relax, L.slow_list, L.n_slow);
         break;

@@ -25,7 +25,7 @@ enum : uint8_t {
 };
 
 enum Layout { LAYOUT_SOA = 0, LAYOUT_AOS = 1 };
-enum Kind { KIND_2POP = 0, KIND_SWAP_COLLIDE = 1, KIND_SWAP_STREAM = 2, KIND_AA_EVEN = 3, KIND_AA_ODD = 4 };
+enum Kind { KIND_2POP = 0, KIND_SWAP_COLLIDE = 1, KIND_SWAP_STREAM = 2, KIND_AA_EVEN = 3, KIND_AA_ODD = 4, KIND_PULL = 5 };
 enum Storage { STORE_F64 = 0, STORE_F32 = 1, STORE_F16 = 2 };
 
 // Cells per thread of the fast step kernels: each lane updates this many
@@ -83,14 +83,14 @@ constexpr int max_step_block(int q, int model, int elem_bytes)
 }
 
 // Waves per SIMD the registers of a fast step kernel must leave room for.
-// FP64 kernels run at the two (AA odd: three) waves the residency cap
-// below allows; the central-moment models on D3Q27 (AA odd) and D3Q19
+// FP64 kernels run at the two (AA odd and 2Pop pull: three) waves the
+// residency cap below allows; the central-moment models on D3Q27 (AA odd) and D3Q19
 // (CM, CHM, cumulant, AA odd) otherwise take one register too many for
 // them (302 and 172-174 registers).
 constexpr int min_step_waves(int q, int elem_bytes, int kind)
 {
     if (elem_bytes != 8) return 1;
-    return (kind == 4 && q == 19) ? 3 : 2;
+    return ((kind == 4 || kind == 5) && q == 19) ? 3 : 2;
 }
 
 // Resident waves per SIMD the fast step kernels are held to (0: no limit),
@@ -100,11 +100,12 @@ constexpr int min_step_waves(int q, int elem_bytes, int kind)
 // (AA: 15.2 -> 16.5 k MLUPS; 2Pop: 14.2 -> 15.2 k); FP32 gains with four on
 // the kinds that touch only their own cell and 2Pop, and FP16 needs every
 // wave it can get. Kinds: 0 2Pop, 1 swap collide, 2 swap stream, 3 AA even,
-// 4 AA odd.
+// 4 AA odd, 5 2Pop pull (FP64: 16.0 k at three to five waves, 15.7 k
+// uncapped; FP32: 32.3 k uncapped, 31.4 k at four).
 inline int step_waves(int elem_bytes, int kind)
 {
-    if (elem_bytes == 8) return kind == 4 ? 3 : 2;
-    if (elem_bytes == 4) return (kind == 4 || kind == 2) ? 0 : 4;
+    if (elem_bytes == 8) return (kind == 4 || kind == 5) ? 3 : 2;
+    if (elem_bytes == 4) return (kind == 4 || kind == 2 || kind == 5) ? 0 : 4;
     return 0;
 }
 

@@ -427,6 +427,89 @@ __device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<S
     }
 }
 
+// Two-population scheme in pull form, beside the push form of Table 1
+// (row 2Pop). The stored state is post-collision with f_out_k in slot kbar,
+// as the AA pattern leaves it after an even step. A step gathers f_k(x) from
+// pop_kbar(x - c_k), or pop_k(x) + pop_kbar(x - c_k) across a wall (the AA
+// odd-step gather), collides, and stores out_kbar(x) <- f_out_k at the
+// cell's own index; the arrays then trade places. The shifted accesses are
+// the reads, which cost this memory system less than shifted writes.
+template <int Q, int MODEL, class ST, int LAYOUT>
+__device__ __forceinline__ void pull_slow(const Field& F, const Relax<real_t<ST>>& p, uint32_t i, uint8_t fl)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    const Acc<ST, LAYOUT, Q, true> a{(typename ST::T*)F.pop, F.stride};
+    const Acc<ST, LAYOUT, Q, true> o{(typename ST::T*)F.out, F.stride};
+    const bool border = fl & FL_BORDER;
+    const Coord c = border ? cell_coord(i, F) : Coord{0, 0, 0};
+    R g[Q];
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k == S::rest) {
+            g[k] = a.ld(i, k);
+        } else {
+            const uint32_t s = neighbour<Q, k, -1>(F, i, border, c);
+            if (is_fluid(F, s)) g[k] = a.ld(s, S::opp(k));
+            else g[k] = a.ld(i, k) + a.ld(s, S::opp(k));
+        }
+    });
+    collide<Q, MODEL, ST::shifted>(g, p);
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        o.st(i, S::opp(k), g[k]);
+    });
+}
+
+template <int Q, int MODEL, class ST, int LAYOUT, int PART>
+__device__ __forceinline__ void cell_pull(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    const Acc<ST, LAYOUT, Q, true> a{(typename ST::T*)F.pop, F.stride};
+    const Acc<ST, LAYOUT, Q, true> o{(typename ST::T*)F.out, F.stride};
+    const uint8_t fl = F.flags[i];
+    if constexpr (PART == PART_SLOW) {
+        pull_slow<Q, MODEL, ST, LAYOUT>(F, p, i, fl);
+    } else {
+        const bool fluid = (fl & FL_TYPE) == FL_FLUID;
+        if constexpr (PART == PART_ALL) {
+            if (fluid && (fl & FL_SLOW)) {
+                pull_slow<Q, MODEL, ST, LAYOUT>(F, p, i, fl);
+                return;
+            }
+        }
+        R g[Q];
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            if constexpr (k == S::rest) g[k] = a.ld(i, k);
+            else g[k] = a.ld_fast(i, S::opp(k), offset<Q, k, -1>(F), F.ntot);
+        });
+        issue_all(g);
+        if (fl & FL_PLANE) {  // across the wall plane: pop_k(x) + pop_kbar(x - c_k)
+            static_for<0, Q>([&](auto K) {
+                constexpr int k = K;
+                if (wall_from<Q, k>(fl)) g[k] += a.ld(i, k);
+            });
+        }
+        collide<Q, MODEL, ST::shifted>(g, p);
+        if (!fluid) {
+            // Wall cells copy their stored terms into the other array, which
+            // keeps every store instruction writing whole cache lines.
+            static_for<0, Q>([&](auto K) {
+                constexpr int k = K;
+                g[k] = a.ld(i, S::opp(k));
+            });
+        } else if (fl & FL_SLOW) {
+            return;  // written by the slow part
+        }
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            o.st(i, S::opp(k), g[k]);
+        });
+    }
+}
+
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND, int PART>
 __device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
 {
@@ -434,7 +517,8 @@ __device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>
     else if constexpr (KIND == KIND_SWAP_COLLIDE) cell_swap_collide<Q, MODEL, ST, LAYOUT>(F, p, i);
     else if constexpr (KIND == KIND_SWAP_STREAM) cell_swap_stream<Q, ST, LAYOUT, PART>(F, i);
     else if constexpr (KIND == KIND_AA_EVEN) cell_aa_even<Q, MODEL, ST, LAYOUT>(F, p, i);
-    else cell_aa_odd<Q, MODEL, ST, LAYOUT, PART>(F, p, i);
+    else if constexpr (KIND == KIND_AA_ODD) cell_aa_odd<Q, MODEL, ST, LAYOUT, PART>(F, p, i);
+    else cell_pull<Q, MODEL, ST, LAYOUT, PART>(F, p, i);
 }
 
 __device__ __forceinline__ uint32_t step_block(const Field& F)

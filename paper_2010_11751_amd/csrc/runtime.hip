@@ -273,6 +273,9 @@ __global__ void __launch_bounds__(256) k_copy_streams(double* __restrict__ dst, 
 
 // --- handle --------------------------------------------------------------------
 
+// Schemes with a second population array.
+static bool two_arrays(int scheme) { return scheme == LBM_2POP || scheme == LBM_2POP_PULL; }
+
 struct lbm_handle {
     lbm_desc d;
     int q = 19;
@@ -338,6 +341,13 @@ struct lbm_handle {
     }
 };
 
+// Whether the stored state is post-collision in slot kbar (AA after an even
+// step, 2Pop pull after any step): read-outs then apply the pending gather.
+static int pending_gather(const lbm_handle* h)
+{
+    return (h->d.scheme == LBM_AA || h->d.scheme == LBM_2POP_PULL) ? h->aa_phase : 0;
+}
+
 extern "C" {
 
 const char* lbm_last_error(void) { return g_error.c_str(); }
@@ -370,7 +380,7 @@ static int validate(const lbm_desc* d)
     if (n > 0x7fffffffLL) return fail(LBM_EUNSUPPORTED, "more than 2^31-1 cells");
     if (d->layout == LBM_SOA && (uint64_t)n * elem_bytes(d->storage_dtype) >= (1ull << 32))
         return fail(LBM_EUNSUPPORTED, "SoA streams above 4 GiB (cells x bytes per value) are not supported");
-    if (d->scheme < LBM_2POP || d->scheme > LBM_AA) return fail(LBM_EINVAL, "unknown scheme");
+    if (d->scheme < LBM_2POP || d->scheme > LBM_2POP_PULL) return fail(LBM_EINVAL, "unknown scheme");
     if (d->collision < LBM_BGK || d->collision > LBM_K) return fail(LBM_EINVAL, "unknown collision model");
     if (d->collision == LBM_K && d->lattice != 19)
         return fail(LBM_EUNSUPPORTED, "the cumulant model is defined on D3Q19 only");
@@ -404,7 +414,7 @@ int lbm_required_bytes(const lbm_desc* d, size_t out[3])
                               2 * (size_t)soa_halo(d->ny, d->nz)) * s
                            : (size_t)n * d->lattice * s;
     out[0] = pop;
-    out[1] = d->scheme == LBM_2POP ? pop : 0;
+    out[1] = two_arrays(d->scheme) ? pop : 0;
     out[2] = (size_t)n;
     return LBM_OK;
 }
@@ -435,7 +445,7 @@ static int init_state(lbm_handle* h, const double* rho, const double* u)
 // the kinds that reach neighbours, the slow part over the listed cells.
 static uint32_t step_lds(const lbm_handle* h, int kind)
 {
-    if (h->lds_override) return kind == KIND_AA_ODD || kind == KIND_2POP || kind == KIND_SWAP_STREAM
+    if (h->lds_override) return kind == KIND_AA_ODD || kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_PULL
                                     ? h->lds_neighbour : h->lds_local;
     return residency_lds(step_waves((int)elem_bytes(h->d.storage_dtype), kind), h->block);
 }
@@ -458,7 +468,7 @@ static int run_kind(lbm_handle* h, int kind)
     if (rc) return rc;
     // With several cells per lane the fast part skips whole groups, so the
     // listed cells need the second launch for the local kinds as well.
-    const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD;
+    const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD || kind == KIND_PULL;
     if ((neighbours || cpt > 1) && h->n_slow > 0) {
         L.op = OP_STEP_SLOW;
         L.block = 256;
@@ -476,7 +486,7 @@ static int run_kind(lbm_handle* h, int kind)
 // waits for the second one before the next launch.
 static int run_kind_overlapped(lbm_handle* h, int kind)
 {
-    const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD;
+    const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD || kind == KIND_PULL;
     if (!h->aux || h->n_slow == 0 || !(neighbours || h->cpt > 1)) return run_kind(h, kind);
     HIP_TRY(hipEventRecord(h->fork, h->stream), "hipEventRecord");
     HIP_TRY(hipStreamWaitEvent(h->aux, h->fork, 0), "hipStreamWaitEvent");
@@ -514,7 +524,13 @@ static int enqueue_steps(lbm_handle* h, int n)
             rc = run_kind_overlapped(h, KIND_SWAP_COLLIDE);
             if (!rc) rc = run_kind_overlapped(h, KIND_SWAP_STREAM);
             if (rc) return rc;
-        } else {
+        } else if (h->d.scheme == LBM_2POP_PULL && h->aa_phase) {
+            // Post-collision state (slot kbar): gather, collide, store into
+            // the other array.
+            rc = run_kind_overlapped(h, KIND_PULL);
+            if (rc) return rc;
+            std::swap(h->pop, h->out);
+        } else {  // AA; and the first 2Pop-pull step from a pre-collision state
             rc = run_kind_overlapped(h, h->aa_phase ? KIND_AA_ODD : KIND_AA_EVEN);
             if (rc) return rc;
             h->aa_phase ^= 1;
@@ -580,6 +596,13 @@ static int capture_steps(lbm_handle* h)
 
 static int enqueue_steps_graph(lbm_handle* h, int n)
 {
+    // 2Pop pull: the entry step (AA even) goes first, so that a graph holds
+    // pull steps only and its even count returns the buffers.
+    if (h->d.scheme == LBM_2POP_PULL && !h->aa_phase && n >= kGraphSteps) {
+        int rc = enqueue_steps(h, 1);
+        if (rc) return rc;
+        --n;
+    }
     while (n >= kGraphSteps) {
         if (!h->graph || h->graph_phase != h->aa_phase || h->graph_pop != h->pop) {
             int rc = capture_steps(h);
@@ -757,7 +780,7 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
     if (d->pop) h->pop_alloc = d->pop;
     else if (alloc(&h->pop_alloc, h->pop_bytes, "pop")) h->own_pop = true;
     else return bail(LBM_ENOMEM, lbm_last_error());
-    if (d->scheme == LBM_2POP) {
+    if (two_arrays(d->scheme)) {
         if (d->out) h->out_alloc = d->out;
         else if (alloc(&h->out_alloc, h->out_bytes, "out")) h->own_out = true;
         else return bail(LBM_ENOMEM, lbm_last_error());
@@ -945,7 +968,7 @@ static int invariants_raw(lbm_handle* h, double* mass, double* ke)
     Launch L = h->base(OP_INVARIANTS);
     L.block = 256;
     L.grid = (uint32_t)h->red_blocks;
-    L.aa_odd = h->d.scheme == LBM_AA ? h->aa_phase : 0;
+    L.aa_odd = pending_gather(h);
     L.d0 = h->partial;
     int rc = run(h, L);
     if (rc) return rc;
@@ -992,7 +1015,7 @@ int lbm_macroscopic(lbm_handle* h, double* rho, double* u)
     if (!rc) rc = stage_out_alloc(h, u, sizeof(double) * 3 * h->ntot, su, &du);
     if (rc) return rc;
     Launch L = h->base(OP_MACRO);
-    L.aa_odd = h->d.scheme == LBM_AA ? h->aa_phase : 0;
+    L.aa_odd = pending_gather(h);
     L.d0 = (double*)dr;
     L.d1 = (double*)du;
     rc = run(h, L);
@@ -1010,7 +1033,7 @@ int lbm_get_populations(lbm_handle* h, double* f)
     int rc = stage_out_alloc(h, f, bytes, s, &df);
     if (rc) return rc;
     Launch L = h->base(OP_GET);
-    L.aa_odd = h->d.scheme == LBM_AA ? h->aa_phase : 0;
+    L.aa_odd = pending_gather(h);
     L.d0 = (double*)df;
     rc = run(h, L);
     if (!rc) rc = stage_out_finish(h, f, bytes, s);
@@ -1031,7 +1054,7 @@ int lbm_get_populations_at(lbm_handle* h, const int64_t* cells, int n, double* f
     if (!rc) rc = stage_out_alloc(h, f, sizeof(double) * n * h->q, so, &df);
     if (rc) return rc;
     Launch L = h->base(OP_GET_CELLS);
-    L.aa_odd = h->d.scheme == LBM_AA ? h->aa_phase : 0;
+    L.aa_odd = pending_gather(h);
     L.cells = (const int64_t*)dc;
     L.d0 = (double*)df;
     L.n = n;

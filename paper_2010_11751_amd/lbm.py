@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(HERE, "liblbm.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-SCHEMES = {"2pop": 0, "swap": 1, "aa": 2}
+SCHEMES = {"2pop": 0, "swap": 1, "aa": 2, "2pop_pull": 3}
 COLLISIONS = {"bgk": 0, "trt": 1, "reg": 2, "rr": 3,
               "nw4": 4, "rm": 5, "hm": 6, "cm": 7, "chm": 8, "k": 9}
 DTYPES = {"f64": 0, "f32": 1, "f16": 2}

@@ -77,7 +77,7 @@ def test_fast_lid_is_rejected(hiplib):
     assert "lid" in hiplib.last_error()
 
 
-@pytest.mark.parametrize("scheme,dtype,layout", [(0, 0, 0), (2, 1, 0), (1, 2, 1)])
+@pytest.mark.parametrize("scheme,dtype,layout", [(0, 0, 0), (2, 1, 0), (1, 2, 1), (3, 0, 0), (3, 2, 1)])
 def test_required_bytes(hiplib, scheme, dtype, layout):
     d = _desc(hiplib, nx=10, ny=11, nz=12, scheme=scheme, storage_dtype=dtype, layout=layout)
     out = (ctypes.c_size_t * 3)()
@@ -90,7 +90,7 @@ def test_required_bytes(hiplib, scheme, dtype, layout):
         assert out[0] == (19 * stride + 2 * halo) * s
     else:
         assert out[0] == 19 * n * s
-    assert out[1] == (out[0] if scheme == 0 else 0)
+    assert out[1] == (out[0] if scheme in (0, 3) else 0)   # 2Pop and 2Pop pull hold two arrays
     assert out[2] == n
 
 
@@ -102,3 +102,16 @@ def test_null_handles_are_rejected(hiplib):
     assert not L.lbm_batch_create(0, None, 2, 0, 0, None)
     L.lbm_destroy(None)
     L.lbm_batch_destroy(None)
+
+
+def test_batch_rejects_swap_and_pull_schemes(hiplib):
+    """The ensemble runs 2Pop or AA; swap and 2Pop pull are valid schemes it
+    does not support (checked before any device call)."""
+    L = hiplib.lib()
+    arr = (hiplib.CavityDesc * 1)()
+    arr[0].nx = arr[0].ny = arr[0].nz = 16
+    arr[0].omega, arr[0].u_lid, arr[0].trt_lambda = 1.8, 0.03, 0.25
+    for scheme in (hiplib.SCHEMES["swap"], hiplib.SCHEMES["2pop_pull"]):
+        assert not L.lbm_batch_create(1, arr, scheme, 1, 1, None)
+        assert "batch schemes" in hiplib.last_error()
+    assert not L.lbm_batch_create(1, arr, 7, 1, 1, None)

@@ -60,7 +60,7 @@ def test_cavity_flags_at_256(lbm):
     assert sim.info().fluid_cells == cav.fluid_cells
 
 
-@pytest.mark.parametrize("scheme", ("2pop", "swap", "aa"))
+@pytest.mark.parametrize("scheme", ("2pop", "swap", "aa", "2pop_pull"))
 @pytest.mark.parametrize("coll", ("bgk", "trt", "reg"))
 def test_cavity_256_fp64_sampled(lbm, scheme, coll):
     cav = W.CAVITY_256
@@ -74,7 +74,7 @@ def test_cavity_256_fp64_sampled(lbm, scheme, coll):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("scheme", ("2pop", "aa"))
+@pytest.mark.parametrize("scheme", ("2pop", "aa", "2pop_pull"))
 def test_cavity_256_fp32_shifted_sampled(lbm, scheme):
     cav = W.CAVITY_256
     sim = lbm.Lattice(19, cav.n, scheme=scheme, collision="bgk", omega=cav.omega, u_lid=cav.u_lid, dtype="f32")

@@ -44,7 +44,7 @@ def cases():
     out = []
     for q in (19, 27):
         for geo in ("cavity", "periodic", "channel"):
-            for scheme in ("2pop", "swap", "aa"):
+            for scheme in ("2pop", "swap", "aa", "2pop_pull"):
                 out.append((q, geo, scheme, "soa"))
         out.append((q, "cavity", "aa", "aos"))
     return out
@@ -70,7 +70,7 @@ def test_custom_geometry_matches_oracle(lbm, q, geo, scheme, layout):
         assert max_err(sim.populations().cpu().numpy(), ref.populations()) <= TOL, n
 
 
-@pytest.mark.parametrize("scheme", ("2pop", "aa"))
+@pytest.mark.parametrize("scheme", ("2pop", "aa", "2pop_pull"))
 def test_custom_geometry_graph_replay_and_reinit(lbm, scheme):
     """Small lattice: steps replay from a captured graph; a later
     lbm_init_equilibrium keeps the per-cell wall terms."""

@@ -19,7 +19,7 @@ from paper_2010_11751_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
-SCHEMES = ("2pop", "swap", "aa")
+SCHEMES = ("2pop", "swap", "aa", "2pop_pull")
 MODELS = ("nw4", "rm", "hm", "cm", "chm", "k")
 RATES = dict(omega=1.71, omega_bulk=1.3, omega3=1.2, omega4=0.9)
 

@@ -16,7 +16,7 @@ from paper_2010_11751_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
-SCHEMES = ("2pop", "swap", "aa")
+SCHEMES = ("2pop", "swap", "aa", "2pop_pull")
 COLLS = ("bgk", "trt", "reg", "rr")
 GEOM = {"cavity": O.CAVITY, "periodic": O.PERIODIC, "channel": O.CHANNEL}
 

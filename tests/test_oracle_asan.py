@@ -29,7 +29,7 @@ for q in (19, 27):
         O.equilibrium(q, 1.02, np.array([0.01, -0.02, 0.03]), O.MODELS[model])
         for layout in (O.SOA, O.AOS):
             cfg.layout = layout
-            for scheme in ("ref", "2pop", "swap", "aa"):
+            for scheme in ("ref", "2pop", "swap", "aa", "2pop_pull"):
                 s = O.Simulation(cfg, scheme)
                 s.step(3)
                 s.macroscopic()

@@ -7,7 +7,7 @@ import pytest
 
 from paper_2010_11751_amd import workloads as W
 
-SCHEMES = ("ref", "2pop", "swap", "aa")
+SCHEMES = ("ref", "2pop", "swap", "aa", "2pop_pull")
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
@@ -60,7 +60,7 @@ def obstacle_types(orc, cfg, seed, fraction=0.1):
     return fl.ravel()
 
 
-@pytest.mark.parametrize("scheme", ("2pop", "swap", "aa"))
+@pytest.mark.parametrize("scheme", ("2pop", "swap", "aa", "2pop_pull"))
 @pytest.mark.parametrize("q", (19, 27))
 def test_obstacles_schemes_match_reference(orc, scheme, q):
     """Cavity with random obstacles whose walls move with random velocities

@@ -10,7 +10,7 @@ import pytest
 
 from paper_2010_11751_amd import workloads as W
 
-SCHEMES = ("ref", "2pop", "swap", "aa")
+SCHEMES = ("ref", "2pop", "swap", "aa", "2pop_pull")
 
 
 def soa(cfg, f_cells):
@@ -131,7 +131,7 @@ def test_schemes_and_layouts_agree_bit_exactly(orc, q, geom, model):
     ref.step(1)
     r4 = ref.populations()
     for layout in (orc.SOA, orc.AOS):
-        for scheme in ("2pop", "swap", "aa"):
+        for scheme in ("2pop", "swap", "aa", "2pop_pull"):
             sim = orc.Simulation(orc.Config(layout=layout, **base), scheme, u=u0)
             sim.step(3)
             assert np.array_equal(sim.populations(), r3), (layout, scheme, 3)
@@ -139,7 +139,7 @@ def test_schemes_and_layouts_agree_bit_exactly(orc, q, geom, model):
             assert np.array_equal(sim.populations(), r4), (layout, scheme, 4)
 
 
-@pytest.mark.parametrize("scheme", ("2pop", "swap", "aa"))
+@pytest.mark.parametrize("scheme", ("2pop", "swap", "aa", "2pop_pull"))
 def test_traversal_order_does_not_matter(orc, scheme):
     """Thread safety by order independence (Sec. 2.3): a random cell order
     gives bit-identical populations."""
