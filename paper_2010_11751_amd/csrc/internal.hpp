@@ -65,6 +65,8 @@ struct Field {
     uint32_t ntot;
     int nx, ny, nz;
     int reverse;           // visit cells in reverse block / list order (traversal-order tests)
+    int custom_walls;      // wall terms set per cell by the caller (else: from type and lid)
+    double lid[3];         // lid velocity of the built-in geometries
 };
 
 // Largest block of the step kernels: the moment-space models (model >= 4)

@@ -427,6 +427,17 @@ __device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<S
     }
 }
 
+// Momentum-exchange term of a wall cell, w_k = -6 t_k c_k . u_w with rho_w = 1
+// (Eq. momentum-exchange, Eq. storage2); u_w = lid velocity on LID cells.
+template <int Q, int K>
+__device__ __forceinline__ double wall_term(uint8_t type, const double (&lid)[3])
+{
+    using S = L<Q>;
+    if (type != FL_LID) return 0.0;
+    const double cu = S::cx(K) * lid[0] + S::cy(K) * lid[1] + S::cz(K) * lid[2];
+    return -6.0 * S::t(K) * cu;
+}
+
 // Two-population scheme in pull form, beside the push form of Table 1
 // (row 2Pop). The stored state is post-collision with f_out_k in slot kbar,
 // as the AA pattern leaves it after an even step. A step gathers f_k(x) from
@@ -494,12 +505,22 @@ __device__ __forceinline__ void cell_pull(const Field& F, const Relax<real_t<ST>
         }
         collide<Q, MODEL, ST::shifted>(g, p);
         if (!fluid) {
-            // Wall cells copy their stored terms into the other array, which
-            // keeps every store instruction writing whole cache lines.
-            static_for<0, Q>([&](auto K) {
-                constexpr int k = K;
-                g[k] = a.ld(i, S::opp(k));
-            });
+            // Wall cells write their terms into the other array, which keeps
+            // every store instruction writing whole cache lines. With the
+            // built-in geometries the terms follow from the cell type and the
+            // lid velocity, as at initialisation, so no reload is needed.
+            if (!F.custom_walls) {
+                const double lid[3] = {F.lid[0], F.lid[1], F.lid[2]};
+                static_for<0, Q>([&](auto K) {
+                    constexpr int k = K;
+                    g[k] = R(wall_term<Q, S::opp(k)>(fl & FL_TYPE, lid));
+                });
+            } else {
+                static_for<0, Q>([&](auto K) {
+                    constexpr int k = K;
+                    g[k] = a.ld(i, S::opp(k));
+                });
+            }
         } else if (fl & FL_SLOW) {
             return;  // written by the slow part
         }
@@ -766,17 +787,6 @@ __global__ void k_set_populations(Field F, const double* __restrict__ f)
         const double v = f[(size_t)k * F.ntot + i];
         a.st(i, k, real_t<ST>(ST::shifted ? v - S::t(k) : v));
     });
-}
-
-// Momentum-exchange term of a wall cell, w_k = -6 t_k c_k . u_w with rho_w = 1
-// (Eq. momentum-exchange, Eq. storage2); u_w = lid velocity on LID cells.
-template <int Q, int K>
-__device__ __forceinline__ double wall_term(uint8_t type, const double (&lid)[3])
-{
-    using S = L<Q>;
-    if (type != FL_LID) return 0.0;
-    const double cu = S::cx(K) * lid[0] + S::cy(K) * lid[1] + S::cz(K) * lid[2];
-    return -6.0 * S::t(K) * cu;
 }
 
 // Fluid cells: the model's equilibrium at (rho, u) (rho = 1, u = 0 when the

@@ -325,6 +325,8 @@ struct lbm_handle {
         F.ny = d.ny;
         F.nz = d.nz;
         F.reverse = reverse_blocks ? 1 : 0;
+        F.custom_walls = custom_walls ? 1 : 0;
+        for (int a = 0; a < 3; ++a) F.lid[a] = d.lid_velocity[a];
         return F;
     }
     Launch base(int op) const
