@@ -5,10 +5,12 @@ u_lid = 0.05), synthetic state at rest, populations resident in HBM. A step
 is one full time step of the method (gather, decode, moments, collision,
 encode, stream with bounce-back) over the whole lattice.
 
-Headline: FP64 storage, BGK, AA-pattern SoA (MLUPS over fluid cells). The
-same JSON line carries the FP32-shifted run of the same workload, the nine
-FP64 scheme x collision combinations, the measured copy-kernel bandwidth,
-the roofline of the dominant kernel and the CPU oracle baseline.
+Headline: FP64 storage, BGK, the fastest scheme on this workload, the
+two-population scheme in pull form (SoA; MLUPS over fluid cells). The same
+JSON line carries the FP32-shifted run, the AA pattern (the paper's fastest
+scheme) in FP64 and FP32, the twelve FP64 scheme x collision combinations,
+the schemes under FP32/FP16 storage, the measured copy-kernel bandwidth, the
+roofline of the dominant kernel and the CPU oracle baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu]
 """
@@ -26,6 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
+HEAD_SCHEME = "2pop_pull"
+KERNEL_LABEL = {"2pop_pull": "2Pop pull", "aa": "AA even/odd"}
+TRAFFIC_KEY = {"2pop_pull": "pull", "aa": "aa"}
 
 
 def kernel_source_hash() -> str:
@@ -343,7 +348,8 @@ def traffic_run(cav):
     torch.cuda.synchronize()
     del a, b
     torch.cuda.empty_cache()
-    for scheme, dtype in (("aa", "f64"), ("aa", "f32"), ("2pop", "f64"), ("swap", "f64"), ("2pop_pull", "f64")):
+    for scheme, dtype in (("aa", "f64"), ("aa", "f32"), ("2pop", "f64"), ("swap", "f64"), ("2pop_pull", "f64"),
+                          ("2pop_pull", "f32")):
         sim = lbm.Lattice(19, cav.n, scheme=scheme, collision="bgk", omega=cav.omega, u_lid=cav.u_lid, dtype=dtype)
         sim.step(4)
         sim.sync()
@@ -401,7 +407,8 @@ def main():
                     help="only the cavity self-convergence study (Re 100, M = 32 / 64 / 128)")
     ap.add_argument("--traffic", action="store_true",
                     help="short run for hardware byte counters: one 1 GiB device copy, then 4 BGK steps of "
-                         "the 256^3 cavity each for AA FP64, AA FP32-shifted, 2Pop FP64 and swap FP64")
+                         "the 256^3 cavity each for AA FP64 / FP32-shifted, 2Pop FP64, swap FP64 and 2Pop pull "
+                         "FP64 / FP32-shifted")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the cavity step runs on a single MI355X; "
@@ -425,10 +432,16 @@ def main():
         validation()
         return
 
-    head = run_case("aa", "bgk", "f64", args.steps, args.warmup, cav, reps=args.reps)
-    print(f"# f64 aa bgk: {head['mlups']:.0f} MLUPS, {head['algorithmic_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
-    f32 = run_case("aa", "bgk", "f32", args.steps, args.warmup, cav, reps=args.reps)
-    print(f"# f32 aa bgk: {f32['mlups']:.0f} MLUPS, {f32['algorithmic_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+    head = run_case(HEAD_SCHEME, "bgk", "f64", args.steps, args.warmup, cav, reps=args.reps)
+    print(f"# f64 {HEAD_SCHEME} bgk: {head['mlups']:.0f} MLUPS, {head['algorithmic_gbs']:.0f} GB/s", file=sys.stderr,
+          flush=True)
+    f32 = run_case(HEAD_SCHEME, "bgk", "f32", args.steps, args.warmup, cav, reps=args.reps)
+    print(f"# f32 {HEAD_SCHEME} bgk: {f32['mlups']:.0f} MLUPS, {f32['algorithmic_gbs']:.0f} GB/s", file=sys.stderr,
+          flush=True)
+    aa64 = run_case("aa", "bgk", "f64", args.steps, args.warmup, cav, reps=args.reps)
+    print(f"# f64 aa bgk: {aa64['mlups']:.0f} MLUPS, {aa64['algorithmic_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+    aa32 = run_case("aa", "bgk", "f32", args.steps, args.warmup, cav, reps=args.reps)
+    print(f"# f32 aa bgk: {aa32['mlups']:.0f} MLUPS, {aa32['algorithmic_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
     sweep = []
     if not args.no_sweep:
         for scheme in ("2pop", "swap", "aa", "2pop_pull"):
@@ -462,12 +475,12 @@ def main():
     streams_gbs = stream_copy_ceiling(cav)
     print(f"# 19-stream copy: {streams_gbs} GB/s", file=sys.stderr, flush=True)
 
-    def roofline(r, key):
+    def roofline(r):
         achieved = r["fluid_cells"] * r["bytes_per_update"] / (r["kernel_avg_ms"] * 1e-3) / 1e9
-        traffic = stored_traffic(key)
+        traffic = stored_traffic(f"{TRAFFIC_KEY[r['scheme']]}_bgk_{r['dtype']}_256")
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                "kernel": "k_step<19,BGK," + r["dtype"] + ",SoA,AA even/odd>",
+                "kernel": "k_step<19,BGK," + r["dtype"] + ",SoA," + KERNEL_LABEL[r["scheme"]] + ">",
                 "bytes_per_launch": r["fluid_cells"] * r["bytes_per_update"],
                 "frac_of_copy": round(achieved / copy_gbs, 4)}
 
@@ -492,14 +505,18 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "D3Q19 lid-driven cavity 256^3 incl. walls, Re=1000, u_lid=0.05, "
-                               "BGK, AA-pattern SoA, FP64 populations",
+                               "BGK, two-population scheme in pull form, SoA, FP64 populations",
+                   "scheme": HEAD_SCHEME,
                    "cells": cav.cells, "fluid_cells": cav.fluid_cells, "omega": round(cav.omega, 6),
                    "parallelism": "single GPU"},
         "hbm_gbs": round(head["algorithmic_gbs"], 1),
-        "roofline": roofline(head, "aa_bgk_f64_256"),
+        "roofline": roofline(head),
         "fp32_shifted": {"value": round(f32["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(f32["ms_per_step"], 5),
                          "hbm_gbs": round(f32["algorithmic_gbs"], 1), "speedup_vs_f64": round(f32["mlups"] / head["mlups"], 3),
-                         "roofline": roofline(f32, "aa_bgk_f32_256")},
+                         "roofline": roofline(f32)},
+        "aa_pattern": {d: {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
+                           "hbm_gbs": round(r["algorithmic_gbs"], 1), "runs_ms_per_step": r["runs_ms_per_step"],
+                           "roofline": roofline(r)} for d, r in (("f64", aa64), ("f32", aa32))},
         "copy_kernel_gbs": round(copy_gbs, 1),
         "stream_copy_19_gbs": streams_gbs,
         "sweep_f64": sweep,
@@ -510,16 +527,16 @@ def main():
     }
     print(json.dumps(out), flush=True)
     if args.jsonl:
-        write_records(args.jsonl, out, head, f32, copy_gbs)
+        write_records(args.jsonl, out, (head, f32, aa64, aa32), copy_gbs)
 
 
-def write_records(path, out, head, f32, copy_gbs):
+def write_records(path, out, heads, copy_gbs):
     """One record per measured run: workload, scheme, collision, dtype,
     MLUPS (fluid and all cells), algorithmic GB/s and its fraction of the HBM
     peak and of the measured copy rate, host cores of the CPU baseline."""
     cores = (out.get("cpu_baseline") or {}).get("cores")
     recs = []
-    for r in (head, f32):
+    for r in heads:
         recs.append({"workload": "cavity_256", "scheme": r["scheme"], "collision": r["collision"], "dtype": r["dtype"],
                      "layout": "soa", "mlups_fluid": round(r["mlups"], 1), "mlups_total": round(r["mlups_all_cells"], 1),
                      "gbs_algorithmic": round(r["algorithmic_gbs"], 1)})
