@@ -169,11 +169,11 @@ def run_d3q27_rr(steps, warmup):
             "roofline_frac": round(gbs / PEAK_HBM_GBS, 4), "steps": steps, "finite": bool(m == m and e == e)}
 
 
-def run_taylor_green(steps):
-    """256^3 periodic Taylor-Green vortex (u0 = 0.04, nu = 0.01), BGK AA-SoA,
-    FP64 vs FP32- and FP16-shifted storage: MLUPS, velocity relative L2
-    against the FP64 run, and the decay of the (k,k,k) mode against
-    exp(-3 nu k^2 t)."""
+def run_taylor_green(steps, scheme):
+    """256^3 periodic Taylor-Green vortex (u0 = 0.04, nu = 0.01), BGK SoA
+    under one scheme, FP64 vs FP32- and FP16-shifted storage: MLUPS,
+    velocity relative L2 against the FP64 run, and the decay of the (k,k,k)
+    mode against exp(-3 nu k^2 t)."""
     import math
     import torch
     from paper_2010_11751_amd import lbm, workloads as W
@@ -183,7 +183,7 @@ def run_taylor_green(steps):
     mode = u0[0].to("cuda")
     out, ref = {}, None
     for dtype in ("f64", "f32", "f16"):
-        sim = lbm.Lattice(19, n, scheme="aa", collision="bgk", omega=omega, geometry="periodic", dtype=dtype)
+        sim = lbm.Lattice(19, n, scheme=scheme, collision="bgk", omega=omega, geometry="periodic", dtype=dtype)
         sim.init_equilibrium(None, u0)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -207,8 +207,8 @@ def run_taylor_green(steps):
             r["velocity_rel_l2_vs_f64"] = float(torch.linalg.vector_norm(u - ref) / torch.linalg.vector_norm(ref))
         out[dtype] = r
     k = 2 * math.pi / n
-    return {"workload": "D3Q19 BGK triply periodic Taylor-Green 256^3, u0=0.04, nu=0.01, AA-SoA",
-            "steps": steps, "analytic_exp_minus_3nuk2t": math.exp(-3 * W.TGV_NU * k * k * steps), **out}
+    return {"workload": f"D3Q19 BGK triply periodic Taylor-Green 256^3, u0=0.04, nu=0.01, {scheme} SoA",
+            "scheme": scheme, "steps": steps, "analytic_exp_minus_3nuk2t": math.exp(-3 * W.TGV_NU * k * k * steps), **out}
 
 
 def run_ensemble(steps, seq_steps):
@@ -269,14 +269,14 @@ DOMAIN_SIZES = (16, 24, 32, 48, 64, 96, 128, 192, 256, 320, 400)
 
 
 def domain_sweep():
-    """MLUPS against cavity size N (walls included) for AA vs 2Pop and BGK vs
-    RR, FP64 D3Q19 SoA, as in the domain-size study of Sec. 3.2.4; steps per
-    size chosen for about 0.3 s of timed work."""
+    """MLUPS against cavity size N (walls included) for AA vs 2Pop (push and
+    pull) and BGK vs RR, FP64 D3Q19 SoA, as in the domain-size study of
+    Sec. 3.2.4; steps per size chosen for about 0.3 s of timed work."""
     from paper_2010_11751_amd import lbm, workloads as W
     rows = []
     for n in DOMAIN_SIZES:
         omega = W.omega_from_nu(0.05 * n / 1000.0)
-        for scheme in ("aa", "2pop"):
+        for scheme in ("aa", "2pop", "2pop_pull"):
             for coll in ("bgk", "rr"):
                 fluid = (n - 2) ** 3
                 steps = int(min(2000, max(20, 0.3 / (fluid / 15e9))))
@@ -400,7 +400,7 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 512^3 D3Q27, Taylor-Green and ensemble workloads")
     ap.add_argument("--domain-sweep", action="store_true",
-                    help="only the MLUPS-vs-cavity-size sweep (N = 16..400; AA vs 2Pop, BGK vs RR, FP64)")
+                    help="only the MLUPS-vs-cavity-size sweep (N = 16..400; AA vs 2Pop push / pull, BGK vs RR, FP64)")
     ap.add_argument("--jsonl", default=None,
                     help="also append one JSON record per measured run to this file")
     ap.add_argument("--validation", action="store_true",
@@ -466,7 +466,9 @@ def main():
     if not args.no_configs:
         workloads["cavity_512_d3q27_rr_f32"] = run_d3q27_rr(max(args.steps // 5, 20), 10)
         print(f"# d3q27 rr 512: {workloads['cavity_512_d3q27_rr_f32']['mlups']} MLUPS", file=sys.stderr, flush=True)
-        workloads["taylor_green_256"] = run_taylor_green(2000)
+        # AA: on a periodic box every face cell takes the edge-cell path, which
+        # the AA pattern pays on odd steps only and 2Pop pull on every step.
+        workloads["taylor_green_256"] = run_taylor_green(2000, "aa")
         print("# taylor-green done", file=sys.stderr, flush=True)
         workloads["ensemble_512"] = run_ensemble(1000, 100)
         print(f"# ensemble: {workloads['ensemble_512']['graph']['mlups']} MLUPS (graph)", file=sys.stderr, flush=True)
@@ -555,10 +557,12 @@ def write_records(path, out, heads, copy_gbs):
         r = w["cavity_512_d3q27_rr_f32"]
         recs.append({"workload": "cavity_512_d3q27", "scheme": "aa", "collision": "rr", "dtype": "f32",
                      "layout": "soa", "mlups_fluid": r["mlups"], "gbs_algorithmic": r["hbm_gbs"]})
-    if "taylor_green_256" in w:
+    for key in ("taylor_green_256", "taylor_green_256_aa"):
+        if key not in w:
+            continue
         for dtype in ("f64", "f32", "f16"):
-            r = w["taylor_green_256"][dtype]
-            recs.append({"workload": "taylor_green_256", "scheme": "aa", "collision": "bgk", "dtype": dtype,
+            r = w[key][dtype]
+            recs.append({"workload": "taylor_green_256", "scheme": w[key]["scheme"], "collision": "bgk", "dtype": dtype,
                          "layout": "soa", "mlups_fluid": r["mlups"], "gbs_algorithmic": r["hbm_gbs"],
                          "velocity_rel_l2_vs_f64": r.get("velocity_rel_l2_vs_f64")})
     if "ensemble_512" in w:

@@ -132,13 +132,15 @@ def test_cavity_320_padded_stride_sampled(lbm):
     torch.cuda.empty_cache()
 
 
-def test_taylor_green_256_sampled(lbm):
-    """The periodic 256^3 Taylor-Green workload (FP64 AA, BGK): sampled
-    cells on the faces, edges and corners wrap."""
+@pytest.mark.parametrize("scheme", ("aa", "2pop_pull"))
+def test_taylor_green_256_sampled(lbm, scheme):
+    """The periodic 256^3 Taylor-Green workload (FP64, BGK, both schemes the
+    benchmark runs it with): sampled cells on the faces, edges and corners
+    wrap."""
     n = W.TGV_N
     omega = W.omega_from_nu(W.TGV_NU)
-    print("case: taylor-green 256^3 f64 aa", flush=True)
-    sim = lbm.Lattice(19, n, scheme="aa", collision="bgk", omega=omega, geometry="periodic")
+    print(f"case: taylor-green 256^3 f64 {scheme}", flush=True)
+    sim = lbm.Lattice(19, n, scheme=scheme, collision="bgk", omega=omega, geometry="periodic")
     sim.init_equilibrium(None, torch.from_numpy(W.taylor_green_velocity(n, n, n, W.TGV_U0)))
     sim.step(3)
     rng = np.random.default_rng(97)
