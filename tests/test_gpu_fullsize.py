@@ -84,12 +84,14 @@ def test_cavity_256_fp32_shifted_sampled(lbm, scheme):
     check_patches(sim, 19, "bgk", cav.omega, cav.u_lid, cells, cav.n, 2e-7)
 
 
-def test_cavity_512_d3q27_rr_fp32_sampled(lbm):
-    """The largest workload: 512^3 (134 M cells, 14.5 GB) D3Q27 RR, FP32
-    shifted storage, AA; needs 64-bit population offsets."""
+@pytest.mark.parametrize("scheme", ("aa", "2pop_pull"))
+def test_cavity_512_d3q27_rr_fp32_sampled(lbm, scheme):
+    """The largest workload: 512^3 (134 M cells, 14.5 GB per array) D3Q27
+    RR, FP32 shifted storage, AA and 2Pop pull as the benchmark runs it;
+    needs 64-bit population offsets."""
     cav = W.CAVITY_512
-    print("case: 512^3 q27 rr f32 aa", flush=True)
-    sim = lbm.Lattice(27, cav.n, scheme="aa", collision="rr", omega=cav.omega, u_lid=cav.u_lid, dtype="f32")
+    print(f"case: 512^3 q27 rr f32 {scheme}", flush=True)
+    sim = lbm.Lattice(27, cav.n, scheme=scheme, collision="rr", omega=cav.omega, u_lid=cav.u_lid, dtype="f32")
     assert sim.info().fluid_cells == cav.fluid_cells
     sim.step(3)
     cells = sample_cells(cav.n, 24, 79)
