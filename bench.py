@@ -471,9 +471,8 @@ def main():
         workloads["cavity_512_d3q27_rr_f32_pull"] = run_d3q27_rr(max(args.steps // 5, 20), 10, HEAD_SCHEME)
         print(f"# d3q27 rr 512 {HEAD_SCHEME}: {workloads['cavity_512_d3q27_rr_f32_pull']['mlups']} MLUPS", file=sys.stderr,
               flush=True)
-        # AA: on a periodic box every face cell takes the edge-cell path, which
-        # the AA pattern pays on odd steps only and 2Pop pull on every step.
-        workloads["taylor_green_256"] = run_taylor_green(2000, "aa")
+        workloads["taylor_green_256"] = run_taylor_green(2000, HEAD_SCHEME)
+        workloads["taylor_green_256_aa"] = run_taylor_green(2000, "aa")
         print("# taylor-green done", file=sys.stderr, flush=True)
         workloads["ensemble_512"] = run_ensemble(1000, 100)
         print(f"# ensemble: {workloads['ensemble_512']['graph']['mlups']} MLUPS (graph)", file=sys.stderr, flush=True)

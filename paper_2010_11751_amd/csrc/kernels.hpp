@@ -472,7 +472,7 @@ __device__ __forceinline__ void pull_slow(const Field& F, const Relax<real_t<ST>
     });
 }
 
-template <int Q, int MODEL, class ST, int LAYOUT, int PART>
+template <int Q, int MODEL, class ST, int LAYOUT, int PART, bool ZWRAP>
 __device__ __forceinline__ void cell_pull(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
 {
     using S = L<Q>;
@@ -490,11 +490,23 @@ __device__ __forceinline__ void cell_pull(const Field& F, const Relax<real_t<ST>
                 return;
             }
         }
+        // ZWRAP variant: z-face cells of a box that wraps in z reach their
+        // wrapped neighbours through a per-lane index correction of +nz
+        // (z = 0, reading z - 1) or -nz (z = nz - 1, reading z + 1).
+        int32_t zp = 0, zm = 0;
+        if (ZWRAP && (fl & FL_ZWRAP)) {
+            if (i % (uint32_t)F.nz == 0) zp = F.nz;
+            else zm = -F.nz;
+        }
         R g[Q];
         static_for<0, Q>([&](auto K) {
             constexpr int k = K;
-            if constexpr (k == S::rest) g[k] = a.ld(i, k);
-            else g[k] = a.ld_fast(i, S::opp(k), offset<Q, k, -1>(F), F.ntot);
+            if constexpr (k == S::rest) {
+                g[k] = a.ld(i, k);
+            } else {
+                const uint32_t j = S::cz(k) > 0 ? i + zp : (S::cz(k) < 0 ? i + zm : i);
+                g[k] = a.ld_fast(j, S::opp(k), offset<Q, k, -1>(F), F.ntot);
+            }
         });
         issue_all(g);
         if (fl & FL_PLANE) {  // across the wall plane: pop_k(x) + pop_kbar(x - c_k)
@@ -521,7 +533,7 @@ __device__ __forceinline__ void cell_pull(const Field& F, const Relax<real_t<ST>
                     g[k] = a.ld(i, S::opp(k));
                 });
             }
-        } else if (fl & FL_SLOW) {
+        } else if ((fl & FL_SLOW) && !(ZWRAP && (fl & FL_ZWRAP))) {
             return;  // written by the slow part
         }
         static_for<0, Q>([&](auto K) {
@@ -539,7 +551,8 @@ __device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>
     else if constexpr (KIND == KIND_SWAP_STREAM) cell_swap_stream<Q, ST, LAYOUT, PART>(F, i);
     else if constexpr (KIND == KIND_AA_EVEN) cell_aa_even<Q, MODEL, ST, LAYOUT>(F, p, i);
     else if constexpr (KIND == KIND_AA_ODD) cell_aa_odd<Q, MODEL, ST, LAYOUT, PART>(F, p, i);
-    else cell_pull<Q, MODEL, ST, LAYOUT, PART>(F, p, i);
+    else if constexpr (KIND == KIND_PULL) cell_pull<Q, MODEL, ST, LAYOUT, PART, false>(F, p, i);
+    else cell_pull<Q, MODEL, ST, LAYOUT, PART, true>(F, p, i);
 }
 
 __device__ __forceinline__ uint32_t step_block(const Field& F)

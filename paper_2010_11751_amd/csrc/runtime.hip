@@ -141,6 +141,7 @@ __global__ void k_flag_hints(uint8_t* fl, int nx, int ny, int nz)
     uint8_t h = 0;
     if (border) {
         h = FL_BORDER | (total ? FL_NEARWALL : 0);
+        if (!total && nz >= 3 && (z == 0 || z == nz - 1) && x > 0 && x < nx - 1 && y > 0 && y < ny - 1) h |= FL_ZWRAP;
     } else if (total) {
         h = FL_NEARWALL;
         for (int a = 0; a < 3; ++a)
@@ -297,6 +298,8 @@ struct lbm_handle {
     int red_blocks = 0;
     uint32_t* slow_list = nullptr;  // fluid cells off the fast path, ascending
     uint32_t n_slow = 0;
+    uint32_t* slow_list_pull = nullptr;  // the same without the z-wrap cells of the pull kernel
+    uint32_t n_slow_pull = 0;            // (one allocation with slow_list)
     int cpt = 1;                    // cells per lane of the fast step kernels
     hipStream_t aux = nullptr;      // runs the near-wall part beside the fast part
     hipEvent_t fork = nullptr, join = nullptr;
@@ -452,6 +455,13 @@ static uint32_t step_lds(const lbm_handle* h, int kind)
     return residency_lds(step_waves((int)elem_bytes(h->d.storage_dtype), kind), h->block);
 }
 
+// Kind of the fast launch: the pull kind has a variant for lattices with
+// z-wrap cells (whose edge list then leaves those cells out).
+static int fast_kind(const lbm_handle* h, int kind)
+{
+    return kind == KIND_PULL && h->n_slow_pull != h->n_slow ? KIND_PULL_Z : kind;
+}
+
 static int run_kind(lbm_handle* h, int kind)
 {
     Launch L = h->base(OP_STEP);
@@ -466,17 +476,20 @@ static int run_kind(lbm_handle* h, int kind)
         L.block = std::min(h->block, 256);
         L.grid = grid_for(((uint64_t)h->ntot + cpt - 1) / cpt, L.block);
     }
+    L.kind = fast_kind(h, kind);
     int rc = run(h, L);
     if (rc) return rc;
+    L.kind = kind;
     // With several cells per lane the fast part skips whole groups, so the
     // listed cells need the second launch for the local kinds as well.
     const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD || kind == KIND_PULL;
-    if ((neighbours || cpt > 1) && h->n_slow > 0) {
+    const uint32_t n_slow = kind == KIND_PULL ? h->n_slow_pull : h->n_slow;
+    if ((neighbours || cpt > 1) && n_slow > 0) {
         L.op = OP_STEP_SLOW;
         L.block = 256;
-        L.grid = grid_for(h->n_slow, 256);
-        L.slow_list = h->slow_list;
-        L.n_slow = h->n_slow;
+        L.grid = grid_for(n_slow, 256);
+        L.slow_list = kind == KIND_PULL ? h->slow_list_pull : h->slow_list;
+        L.n_slow = n_slow;
         rc = run(h, L);
     }
     return rc;
@@ -489,20 +502,21 @@ static int run_kind(lbm_handle* h, int kind)
 static int run_kind_overlapped(lbm_handle* h, int kind)
 {
     const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD || kind == KIND_PULL;
-    if (!h->aux || h->n_slow == 0 || !(neighbours || h->cpt > 1)) return run_kind(h, kind);
+    const uint32_t n_slow = kind == KIND_PULL ? h->n_slow_pull : h->n_slow;
+    if (!h->aux || n_slow == 0 || !(neighbours || h->cpt > 1)) return run_kind(h, kind);
     HIP_TRY(hipEventRecord(h->fork, h->stream), "hipEventRecord");
     HIP_TRY(hipStreamWaitEvent(h->aux, h->fork, 0), "hipStreamWaitEvent");
     Launch S = h->base(OP_STEP_SLOW);
     S.kind = kind;
     S.block = 256;
-    S.grid = grid_for(h->n_slow, 256);
-    S.slow_list = h->slow_list;
-    S.n_slow = h->n_slow;
+    S.grid = grid_for(n_slow, 256);
+    S.slow_list = kind == KIND_PULL ? h->slow_list_pull : h->slow_list;
+    S.n_slow = n_slow;
     hipError_t e = h->launch(S, h->aux);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     HIP_TRY(hipEventRecord(h->join, h->aux), "hipEventRecord");
     Launch L = h->base(OP_STEP);
-    L.kind = kind;
+    L.kind = fast_kind(h, kind);
     L.lds = step_lds(h, kind);
     if (h->cpt > 1) {
         L.block = std::min(h->block, 256);
@@ -705,7 +719,7 @@ static int build_tables(lbm_handle* h)
     std::vector<uint8_t> fl((size_t)h->ntot);
     HIP_TRY(hipMemcpy(fl.data(), h->flags, (size_t)h->ntot, hipMemcpyDeviceToHost), "flag read-back");
     const int64_t cpt = h->cpt;
-    std::vector<uint32_t> slow;
+    std::vector<uint32_t> slow, pull;
     for (int64_t g0 = 0; g0 < h->ntot; g0 += cpt) {
         // a group is fast when it is whole and every cell in it is a fast fluid cell
         bool fast = g0 + cpt <= h->ntot;
@@ -715,17 +729,26 @@ static int build_tables(lbm_handle* h)
             fast = fast && (fl[i] & off_path) == FL_FLUID;
         if (fast) continue;
         for (int64_t i = g0; i < g0 + cpt && i < h->ntot; ++i)
-            if ((fl[i] & FL_TYPE) == FL_FLUID) slow.push_back((uint32_t)i);
+            if ((fl[i] & FL_TYPE) == FL_FLUID) {
+                slow.push_back((uint32_t)i);
+                if (cpt > 1 || !(fl[i] & FL_ZWRAP)) pull.push_back((uint32_t)i);
+            }
     }
     if (h->slow_list) {
         HIP_TRY(hipFree(h->slow_list), "hipFree");
         h->slow_list = nullptr;
     }
     h->n_slow = (uint32_t)slow.size();
+    h->n_slow_pull = (uint32_t)pull.size();
+    h->slow_list_pull = nullptr;
     if (h->n_slow) {
-        HIP_TRY(hipMalloc((void**)&h->slow_list, sizeof(uint32_t) * slow.size()), "hipMalloc slow list");
+        HIP_TRY(hipMalloc((void**)&h->slow_list, sizeof(uint32_t) * (slow.size() + pull.size())), "hipMalloc slow list");
         HIP_TRY(hipMemcpy(h->slow_list, slow.data(), sizeof(uint32_t) * slow.size(), hipMemcpyHostToDevice),
                 "slow list");
+        h->slow_list_pull = h->slow_list + slow.size();
+        if (!pull.empty())
+            HIP_TRY(hipMemcpy(h->slow_list_pull, pull.data(), sizeof(uint32_t) * pull.size(), hipMemcpyHostToDevice),
+                    "slow list");
     }
     if (h->n_slow > 0 && !h->aux && !std::getenv("LBM_NO_OVERLAP")) {
         HIP_TRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking), "auxiliary stream");
