@@ -20,8 +20,9 @@ enum : uint8_t {
     FL_PLANE_SHIFT = 2,
     FL_PLANE = 0x1C,
     // Fluid cell on a z face of a box that wraps in z, with x and y inside the
-    // box and no solid neighbour: the pull kernel's fast path corrects its
-    // z-wrapped reads itself (the other kinds list the cell as a border cell).
+    // box and no solid neighbour: the fast paths of the pull and AA odd kernels
+    // correct their z-wrapped accesses themselves (the other kinds list the
+    // cell as a border cell).
     FL_ZWRAP = 0x20,
     FL_BORDER = 0x40,    // fluid cell on a box face: neighbours may wrap
     FL_NEARWALL = 0x80,  // fluid cell with any other pattern of non-fluid neighbours
@@ -29,10 +30,11 @@ enum : uint8_t {
 };
 
 enum Layout { LAYOUT_SOA = 0, LAYOUT_AOS = 1 };
-// KIND_PULL_Z: the pull kernel's fast part for lattices with FL_ZWRAP cells.
+// KIND_PULL_Z, KIND_AA_ODD_Z: the fast parts of the pull and AA odd kernels
+// for lattices with FL_ZWRAP cells.
 enum Kind {
     KIND_2POP = 0, KIND_SWAP_COLLIDE = 1, KIND_SWAP_STREAM = 2, KIND_AA_EVEN = 3, KIND_AA_ODD = 4, KIND_PULL = 5,
-    KIND_PULL_Z = 6
+    KIND_PULL_Z = 6, KIND_AA_ODD_Z = 7
 };
 enum Storage { STORE_F64 = 0, STORE_F32 = 1, STORE_F16 = 2 };
 
@@ -100,7 +102,7 @@ constexpr int max_step_block(int q, int model, int elem_bytes)
 constexpr int min_step_waves(int q, int elem_bytes, int kind)
 {
     if (elem_bytes != 8) return 1;
-    return ((kind == 4 || kind == 5 || kind == 6) && q == 19) ? 3 : 2;
+    return ((kind == 4 || kind == 5 || kind == 6 || kind == 7) && q == 19) ? 3 : 2;
 }
 
 // Resident waves per SIMD the fast step kernels are held to (0: no limit),
@@ -111,11 +113,12 @@ constexpr int min_step_waves(int q, int elem_bytes, int kind)
 // the kinds that touch only their own cell and 2Pop, and FP16 needs every
 // wave it can get. Kinds: 0 2Pop, 1 swap collide, 2 swap stream, 3 AA even,
 // 4 AA odd, 5 2Pop pull (FP64: 16.0 k at three to five waves, 15.7 k
-// uncapped; FP32: 32.3 k uncapped, 31.4 k at four), 6 its z-wrap variant.
+// uncapped; FP32: 32.3 k uncapped, 31.4 k at four), 6 and 7 the z-wrap
+// variants of 5 and 4.
 inline int step_waves(int elem_bytes, int kind)
 {
-    if (elem_bytes == 8) return (kind == 4 || kind == 5 || kind == 6) ? 3 : 2;
-    if (elem_bytes == 4) return (kind == 4 || kind == 2 || kind == 5 || kind == 6) ? 0 : 4;
+    if (elem_bytes == 8) return (kind == 4 || kind >= 5) ? 3 : 2;
+    if (elem_bytes == 4) return (kind == 4 || kind == 2 || kind >= 5) ? 0 : 4;
     return 0;
 }
 

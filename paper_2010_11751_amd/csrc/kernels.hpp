@@ -384,7 +384,7 @@ __device__ __forceinline__ void aa_odd_slow(const Field& F, const Relax<real_t<S
     });
 }
 
-template <int Q, int MODEL, class ST, int LAYOUT, int PART>
+template <int Q, int MODEL, class ST, int LAYOUT, int PART, bool ZWRAP>
 __device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
 {
     using S = L<Q>;
@@ -400,11 +400,23 @@ __device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<S
                 return;
             }
         }
+        // ZWRAP variant: z-face cells of a box that wraps in z reach their
+        // wrapped neighbours through a per-lane index correction: +nz at
+        // z = 0 (reading z - 1, writing z - 1), -nz at z = nz - 1.
+        int32_t zp = 0, zm = 0;
+        if (ZWRAP && (fl & FL_ZWRAP)) {
+            if (i % (uint32_t)F.nz == 0) zp = F.nz;
+            else zm = -F.nz;
+        }
         R g[Q];
         static_for<0, Q>([&](auto K) {
             constexpr int k = K;
-            if constexpr (k == S::rest) g[k] = a.ld(i, k);
-            else g[k] = a.ld_fast(i, S::opp(k), offset<Q, k, -1>(F), F.ntot);
+            if constexpr (k == S::rest) {
+                g[k] = a.ld(i, k);
+            } else {
+                const uint32_t j = S::cz(k) > 0 ? i + zp : (S::cz(k) < 0 ? i + zm : i);
+                g[k] = a.ld_fast(j, S::opp(k), offset<Q, k, -1>(F), F.ntot);
+            }
         });
         issue_all(g);
         if (fl & FL_PLANE) {  // pull across the wall plane: pop_k(x) + pop_kbar(x - c_k)
@@ -414,11 +426,12 @@ __device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<S
             });
         }
         collide<Q, MODEL, ST::shifted>(g, p);
-        if (!take_fast<PART>(fl)) return;
+        if (!take_fast<PART>(fl) && !(ZWRAP && (fl & FL_ZWRAP))) return;
         static_for<0, Q>([&](auto K) {
             constexpr int k = K;
             if (!wall_to<Q, k>(fl)) {
-                a.raw_st_shift(i, k, offset<Q, k, 1>(F), typename ST::T(g[k]));
+                const uint32_t j = S::cz(k) > 0 ? i + zm : (S::cz(k) < 0 ? i + zp : i);
+                a.raw_st_shift(j, k, offset<Q, k, 1>(F), typename ST::T(g[k]));
             } else {  // push across the wall plane: pop_kbar(x) <- f_out_k + pop_k(x + c_k)
                 const R w = R(a.raw_ld_shift(i, k, offset<Q, k, 1>(F)));
                 a.st(i, S::opp(k), g[k] + w);
@@ -550,7 +563,8 @@ __device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>
     else if constexpr (KIND == KIND_SWAP_COLLIDE) cell_swap_collide<Q, MODEL, ST, LAYOUT>(F, p, i);
     else if constexpr (KIND == KIND_SWAP_STREAM) cell_swap_stream<Q, ST, LAYOUT, PART>(F, i);
     else if constexpr (KIND == KIND_AA_EVEN) cell_aa_even<Q, MODEL, ST, LAYOUT>(F, p, i);
-    else if constexpr (KIND == KIND_AA_ODD) cell_aa_odd<Q, MODEL, ST, LAYOUT, PART>(F, p, i);
+    else if constexpr (KIND == KIND_AA_ODD) cell_aa_odd<Q, MODEL, ST, LAYOUT, PART, false>(F, p, i);
+    else if constexpr (KIND == KIND_AA_ODD_Z) cell_aa_odd<Q, MODEL, ST, LAYOUT, PART, true>(F, p, i);
     else if constexpr (KIND == KIND_PULL) cell_pull<Q, MODEL, ST, LAYOUT, PART, false>(F, p, i);
     else cell_pull<Q, MODEL, ST, LAYOUT, PART, true>(F, p, i);
 }

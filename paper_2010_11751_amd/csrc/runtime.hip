@@ -298,8 +298,8 @@ struct lbm_handle {
     int red_blocks = 0;
     uint32_t* slow_list = nullptr;  // fluid cells off the fast path, ascending
     uint32_t n_slow = 0;
-    uint32_t* slow_list_pull = nullptr;  // the same without the z-wrap cells of the pull kernel
-    uint32_t n_slow_pull = 0;            // (one allocation with slow_list)
+    uint32_t* slow_list_z = nullptr;  // the same without the z-wrap cells, which the fast
+    uint32_t n_slow_z = 0;            // pull and AA odd kernels handle (one allocation)
     int cpt = 1;                    // cells per lane of the fast step kernels
     hipStream_t aux = nullptr;      // runs the near-wall part beside the fast part
     hipEvent_t fork = nullptr, join = nullptr;
@@ -455,11 +455,14 @@ static uint32_t step_lds(const lbm_handle* h, int kind)
     return residency_lds(step_waves((int)elem_bytes(h->d.storage_dtype), kind), h->block);
 }
 
-// Kind of the fast launch: the pull kind has a variant for lattices with
-// z-wrap cells (whose edge list then leaves those cells out).
+// Kind of the fast launch: the pull and AA odd kinds have variants for
+// lattices with z-wrap cells, whose edge list then leaves those cells out.
+static bool zwrap_kind(int kind) { return kind == KIND_PULL || kind == KIND_AA_ODD; }
+
 static int fast_kind(const lbm_handle* h, int kind)
 {
-    return kind == KIND_PULL && h->n_slow_pull != h->n_slow ? KIND_PULL_Z : kind;
+    if (!zwrap_kind(kind) || h->n_slow_z == h->n_slow) return kind;
+    return kind == KIND_PULL ? KIND_PULL_Z : KIND_AA_ODD_Z;
 }
 
 static int run_kind(lbm_handle* h, int kind)
@@ -483,12 +486,12 @@ static int run_kind(lbm_handle* h, int kind)
     // With several cells per lane the fast part skips whole groups, so the
     // listed cells need the second launch for the local kinds as well.
     const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD || kind == KIND_PULL;
-    const uint32_t n_slow = kind == KIND_PULL ? h->n_slow_pull : h->n_slow;
+    const uint32_t n_slow = zwrap_kind(kind) ? h->n_slow_z : h->n_slow;
     if ((neighbours || cpt > 1) && n_slow > 0) {
         L.op = OP_STEP_SLOW;
         L.block = 256;
         L.grid = grid_for(n_slow, 256);
-        L.slow_list = kind == KIND_PULL ? h->slow_list_pull : h->slow_list;
+        L.slow_list = zwrap_kind(kind) ? h->slow_list_z : h->slow_list;
         L.n_slow = n_slow;
         rc = run(h, L);
     }
@@ -502,7 +505,7 @@ static int run_kind(lbm_handle* h, int kind)
 static int run_kind_overlapped(lbm_handle* h, int kind)
 {
     const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD || kind == KIND_PULL;
-    const uint32_t n_slow = kind == KIND_PULL ? h->n_slow_pull : h->n_slow;
+    const uint32_t n_slow = zwrap_kind(kind) ? h->n_slow_z : h->n_slow;
     if (!h->aux || n_slow == 0 || !(neighbours || h->cpt > 1)) return run_kind(h, kind);
     HIP_TRY(hipEventRecord(h->fork, h->stream), "hipEventRecord");
     HIP_TRY(hipStreamWaitEvent(h->aux, h->fork, 0), "hipStreamWaitEvent");
@@ -510,7 +513,7 @@ static int run_kind_overlapped(lbm_handle* h, int kind)
     S.kind = kind;
     S.block = 256;
     S.grid = grid_for(n_slow, 256);
-    S.slow_list = kind == KIND_PULL ? h->slow_list_pull : h->slow_list;
+    S.slow_list = zwrap_kind(kind) ? h->slow_list_z : h->slow_list;
     S.n_slow = n_slow;
     hipError_t e = h->launch(S, h->aux);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -739,15 +742,15 @@ static int build_tables(lbm_handle* h)
         h->slow_list = nullptr;
     }
     h->n_slow = (uint32_t)slow.size();
-    h->n_slow_pull = (uint32_t)pull.size();
-    h->slow_list_pull = nullptr;
+    h->n_slow_z = (uint32_t)pull.size();
+    h->slow_list_z = nullptr;
     if (h->n_slow) {
         HIP_TRY(hipMalloc((void**)&h->slow_list, sizeof(uint32_t) * (slow.size() + pull.size())), "hipMalloc slow list");
         HIP_TRY(hipMemcpy(h->slow_list, slow.data(), sizeof(uint32_t) * slow.size(), hipMemcpyHostToDevice),
                 "slow list");
-        h->slow_list_pull = h->slow_list + slow.size();
+        h->slow_list_z = h->slow_list + slow.size();
         if (!pull.empty())
-            HIP_TRY(hipMemcpy(h->slow_list_pull, pull.data(), sizeof(uint32_t) * pull.size(), hipMemcpyHostToDevice),
+            HIP_TRY(hipMemcpy(h->slow_list_z, pull.data(), sizeof(uint32_t) * pull.size(), hipMemcpyHostToDevice),
                     "slow list");
     }
     if (h->n_slow > 0 && !h->aux && !std::getenv("LBM_NO_OVERLAP")) {
