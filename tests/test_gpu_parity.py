@@ -91,6 +91,28 @@ def test_wrapping_geometries_from_a_velocity_field(lbm, q, geometry, scheme):
     assert max_err(sim.populations().cpu().numpy(), ref.populations()) <= TOL
 
 
+@pytest.mark.parametrize("layout", ("soa", "aos"))
+@pytest.mark.parametrize("scheme", ("aa", "2pop_pull"))
+@pytest.mark.parametrize("q", (19, 27))
+def test_periodic_z_faces_on_the_fast_path(lbm, q, scheme, layout):
+    """Periodic boxes: z-face cells whose x and y lie inside the box take
+    the fast AA odd / pull kernels with a per-lane +-nz index correction
+    (eager steps). nz = 3 is the smallest box with such cells; nz = 70 puts
+    row ends inside waves."""
+    for n3 in ((7, 6, 3), (6, 5, 70)):
+        nx, ny, nz = n3
+        print(f"case: periodic z faces q={q} {scheme} {layout} {nx}x{ny}x{nz}", flush=True)
+        u0 = W.random_velocity(67, nx * ny * nz, amp=0.04).T.copy()
+        sim = lbm.Lattice(q, nx, ny, nz, scheme=scheme, collision="trt", omega=1.6, geometry="periodic",
+                          layout=layout)
+        sim.init_equilibrium(None, torch.from_numpy(u0))
+        ref = O.Simulation(oracle_cfg(q, nx, ny, nz, "trt", 1.6, geometry="periodic"), "ref", u=u0)
+        for n in (5, 1):   # odd, then even step count
+            sim.step(n)
+            ref.step(n)
+            assert max_err(sim.populations().cpu().numpy(), ref.populations()) <= TOL, (n3, n)
+
+
 @pytest.mark.parametrize("q", (19, 27))
 def test_rr_equilibrium_initialisation(lbm, q):
     n = 7
