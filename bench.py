@@ -405,6 +405,8 @@ def main():
                     help="only the MLUPS-vs-cavity-size sweep (N = 16..400; AA vs 2Pop push / pull, BGK vs RR, FP64)")
     ap.add_argument("--jsonl", default=None,
                     help="also append one JSON record per measured run to this file")
+    ap.add_argument("--taylor-green", action="store_true",
+                    help="only the periodic 256^3 Taylor-Green workload (2Pop pull and AA; FP64 / FP32 / FP16)")
     ap.add_argument("--validation", action="store_true",
                     help="only the cavity self-convergence study (Re 100, M = 32 / 64 / 128)")
     ap.add_argument("--traffic", action="store_true",
@@ -432,6 +434,10 @@ def main():
         return
     if args.validation:
         validation()
+        return
+    if args.taylor_green:
+        print(json.dumps({"taylor_green_256": run_taylor_green(args.steps, HEAD_SCHEME),
+                          "taylor_green_256_aa": run_taylor_green(args.steps, "aa")}), flush=True)
         return
 
     head = run_case(HEAD_SCHEME, "bgk", "f64", args.steps, args.warmup, cav, reps=args.reps)
