@@ -34,6 +34,12 @@
  *   reference step, schemes ... pinned (np.roll brute force, bounce-back
  *                               permutation, mass conservation, schemes and
  *                               layouts agree bit for bit, shuffled order)
+ *   per-cell reference step ... pinned (equals the whole-lattice reference
+ *                               step cell by cell, bit for bit, in every
+ *                               geometry, model and lattice)
+ *   invariants ................ pinned (mass and kinetic energy of states
+ *                               built from given rho and u fields equal
+ *                               sum rho and 1/2 sum rho |u|^2 of those fields)
  */
 #include <math.h>
 #ifdef _OPENMP
