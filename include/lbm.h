@@ -136,6 +136,9 @@ typedef struct lbm_desc {
     void *pop;            /* optional caller-owned device buffers (see         */
     void *out;            /*   lbm_required_bytes); caller keeps ownership and */
     void *flags;          /*   must keep them alive until lbm_destroy          */
+    size_t pop_bytes;     /* sizes in bytes of the caller buffers above; each  */
+    size_t out_bytes;     /*   given buffer must hold at least what            */
+    size_t flags_bytes;   /*   lbm_required_bytes reports, else LBM_EINVAL     */
 } lbm_desc;
 
 /* Per-handle facts for reporting. */
@@ -167,7 +170,11 @@ int lbm_required_bytes(const lbm_desc *d, size_t out[3]);
 lbm_handle *lbm_create(int lattice, int nx, int ny, int nz, int scheme, int collision,
                        double omega, double u_lid, int storage_dtype);
 
-/* Create from a full description; same initial state as lbm_create. */
+/* Create from a full description; same initial state as lbm_create. Caller
+ * buffers (pop, out, flags) are checked before any device work: each must be
+ * 256-byte aligned and its size field (pop_bytes, out_bytes, flags_bytes) at
+ * least what lbm_required_bytes reports; otherwise NULL with LBM_EINVAL (the
+ * library never writes past a caller buffer it was told the size of). */
 lbm_handle *lbm_create_ex(const lbm_desc *d);
 
 /* Free library-owned buffers and the handle (caller buffers are untouched). */

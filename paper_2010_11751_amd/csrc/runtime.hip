@@ -761,9 +761,33 @@ static int build_tables(lbm_handle* h)
     return LBM_OK;
 }
 
+// Caller buffers: 256-byte aligned and at least as large as
+// lbm_required_bytes reports, checked before any device work.
+static int check_caller_buffers(const lbm_desc* d)
+{
+    size_t req[3];
+    if (int rc = lbm_required_bytes(d, req)) return rc;
+    struct {
+        const void* p;
+        size_t have, need;
+        const char* name;
+    } const bufs[3] = {{d->pop, d->pop_bytes, req[0], "pop"},
+                       {two_arrays(d->scheme) ? d->out : nullptr, d->out_bytes, req[1], "out"},
+                       {d->flags, d->flags_bytes, req[2], "flags"}};
+    for (const auto& b : bufs) {
+        if (!b.p) continue;
+        if ((uintptr_t)b.p % 256 != 0)
+            return fail(LBM_EINVAL, std::string("caller buffer ") + b.name + " must be 256-byte aligned");
+        if (b.have < b.need)
+            return fail(LBM_EINVAL, std::string("caller buffer ") + b.name + " holds " + std::to_string(b.have) +
+                                        " bytes, " + std::to_string(b.need) + " needed (lbm_required_bytes)");
+    }
+    return LBM_OK;
+}
+
 lbm_handle* lbm_create_ex(const lbm_desc* d)
 {
-    if (validate(d)) return nullptr;
+    if (validate(d) || check_caller_buffers(d)) return nullptr;
     lbm_handle* h = new lbm_handle();
     h->d = *d;
     h->q = d->lattice;
@@ -816,8 +840,6 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
     if (d->flags) h->flags = (uint8_t*)d->flags;
     else if (alloc((void**)&h->flags, h->flag_bytes, "flags")) h->own_flags = true;
     else return bail(LBM_ENOMEM, lbm_last_error());
-    for (void* p : {h->pop_alloc, h->out_alloc, (void*)h->flags})
-        if (p && ((uintptr_t)p % 256) != 0) return bail(LBM_EINVAL, "caller buffers must be 256-byte aligned");
     {
         const size_t skip = d->layout == LBM_SOA ? (size_t)soa_halo(d->ny, d->nz) * elem_bytes(d->storage_dtype) : 0;
         h->pop = (char*)h->pop_alloc + skip;

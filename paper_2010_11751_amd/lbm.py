@@ -43,7 +43,8 @@ class Desc(ctypes.Structure):
                 ("omega", ctypes.c_double), ("trt_lambda", ctypes.c_double), ("omega_bulk", ctypes.c_double),
                 ("omega3", ctypes.c_double), ("omega4", ctypes.c_double),
                 ("lid_velocity", ctypes.c_double * 3), ("stream", ctypes.c_void_p),
-                ("pop", ctypes.c_void_p), ("out", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+                ("pop", ctypes.c_void_p), ("out", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+                ("pop_bytes", ctypes.c_size_t), ("out_bytes", ctypes.c_size_t), ("flags_bytes", ctypes.c_size_t)]
 
 
 class Info(ctypes.Structure):
@@ -226,6 +227,8 @@ class Lattice:
             d.stream = self.stream.cuda_stream
             d.pop, d.out, d.flags = self._pop.data_ptr(), (self._out.data_ptr() if self._out is not None else None), \
                 self._flags.data_ptr()
+            d.pop_bytes, d.flags_bytes = self._pop.numel(), self._flags.numel()
+            d.out_bytes = self._out.numel() if self._out is not None else 0
             h = lib().lbm_create_ex(ctypes.byref(d))
         if not h:
             raise LBMError(EINVAL, last_error())

@@ -115,3 +115,31 @@ def test_batch_rejects_swap_and_pull_schemes(hiplib):
         assert not L.lbm_batch_create(1, arr, scheme, 1, 1, None)
         assert "batch schemes" in hiplib.last_error()
     assert not L.lbm_batch_create(1, arr, 7, 1, 1, None)
+
+
+@pytest.mark.parametrize("scheme", (0, 3))
+def test_undersized_or_misaligned_caller_buffers_are_rejected(hiplib, scheme):
+    """Caller buffers smaller than lbm_required_bytes reports, or not 256-byte
+    aligned, are refused before any device work (the pointers below are never
+    dereferenced: creation stops at the check)."""
+    L = hiplib.lib()
+    d = _desc(hiplib, nx=10, ny=11, nz=12, scheme=scheme)
+    req = (ctypes.c_size_t * 3)()
+    assert L.lbm_required_bytes(ctypes.byref(d), req) == 0
+    fake = 1 << 40   # 256-byte aligned, never touched
+    cases = [("pop", "pop_bytes", req[0]), ("flags", "flags_bytes", req[2]), ("out", "out_bytes", req[1])]
+    for ptr, size, need in cases:
+        d = _desc(hiplib, nx=10, ny=11, nz=12, scheme=scheme)
+        setattr(d, ptr, fake)
+        setattr(d, size, need - 1)
+        assert not L.lbm_create_ex(ctypes.byref(d))
+        assert f"caller buffer {ptr} holds {need - 1} bytes, {need} needed" in hiplib.last_error()
+        d = _desc(hiplib, nx=10, ny=11, nz=12, scheme=scheme)
+        setattr(d, ptr, fake + 64)
+        setattr(d, size, need)
+        assert not L.lbm_create_ex(ctypes.byref(d))
+        assert "256-byte aligned" in hiplib.last_error()
+    # a buffer given without its size is refused as well
+    d = _desc(hiplib, nx=10, ny=11, nz=12, scheme=scheme, pop=fake)
+    assert not L.lbm_create_ex(ctypes.byref(d))
+    assert "caller buffer pop holds 0 bytes" in hiplib.last_error()
