@@ -233,6 +233,20 @@ int lbm_get_flags(lbm_handle *h, uint8_t *flags);
  * of the natural state, reduced in FP64 in a fixed order (host pointers). */
 int lbm_invariants(lbm_handle *h, double *mass, double *kinetic_energy);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the global
+ * mass and kinetic energy of lbm_invariants, computed by the same kernels in
+ * the same order, with their partial sums in a fixed device array of the
+ * library instead of per-handle memory. result[0] = mass, result[1] = kinetic
+ * energy; result follows ptr_kind: a device pointer is written asynchronously
+ * on the handle's stream (no wait), a host pointer is written before return.
+ * Allocates nothing and calls no allocating routine. Limit: lattices of at
+ * most 2^25 cells (larger ones return LBM_EINVAL); the array takes 2 MiB per
+ * GPU for the life of the process. All calls on one GPU share that GPU's
+ * array: calls whose executions overlap on one GPU (different streams, or
+ * different threads) race and must be ordered by the caller. */
+int lbm_invariants_noalloc(lbm_handle *h, double *result);
+
 /* Linear index of the neighbour x + c_k of each listed cell, as the step
  * kernels compute it (wrapping on periodic axes): out[j*Q + k] for
  * cells[j], j < n. Both arrays follow ptr_kind. */

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -272,6 +273,40 @@ __global__ void __launch_bounds__(256) k_copy_streams(double* __restrict__ dst, 
 
 }  // namespace
 
+// --- scratch of the no-allocation invariants entry point -----------------------
+// lbm_invariants_noalloc keeps its per-block partial sums (two per block of
+// 256 cells) and, for host outputs, its two results in this file-scope device
+// array instead of the handle's reduction buffer, so that the call allocates
+// nothing. It serves lattices of up to kNoAllocMaxCells cells. Each GPU holds
+// its own copy, at its own address, until the process ends. In host code the
+// name `scratch` is only a stand-in: its device address is looked up once per
+// device at handle creation (hipGetSymbolAddress, that device current), and
+// only that address is ever passed to kernels or copies.
+constexpr int64_t kNoAllocMaxCells = int64_t(1) << 25;
+constexpr size_t kNoAllocDoubles = 2 * (size_t)(kNoAllocMaxCells / 256) + 2;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kNoAllocMaxDevices] = {};  // device address of `scratch`, per device
+
+// Device address of `scratch` on the current device (looked up on first use).
+int scratch_address(int device, double** out)
+{
+    if (device < 0 || device >= kNoAllocMaxDevices)
+        return fail(LBM_EUNSUPPORTED, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[device] = (double*)p;
+    }
+    *out = g_scratch_ptr[device];
+    return LBM_OK;
+}
+}  // namespace
+
 // --- handle --------------------------------------------------------------------
 
 // Schemes with a second population array.
@@ -296,6 +331,8 @@ struct lbm_handle {
     int block = 256;
     double* partial = nullptr;  // invariant partial sums (2 per block) + 2 results
     int red_blocks = 0;
+    int device = 0;                 // GPU the buffers live on (current at creation)
+    double* scratch = nullptr;      // that GPU's copy of `scratch` (lbm_invariants_noalloc)
     uint32_t* slow_list = nullptr;  // fluid cells off the fast path, ascending
     uint32_t n_slow = 0;
     uint32_t* slow_list_z = nullptr;  // the same without the z-wrap cells, which the fast
@@ -849,6 +886,11 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
     h->red_blocks = (int)grid_for((uint64_t)h->ntot, 256);
     if (!alloc((void**)&h->partial, sizeof(double) * (2 * (size_t)h->red_blocks + 2), "reduction"))
         return bail(LBM_ENOMEM, lbm_last_error());
+    {
+        hipError_t e = hipGetDevice(&h->device);
+        if (e != hipSuccess) return bail(LBM_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+        if (int rc = scratch_address(h->device, &h->scratch)) return bail(rc, lbm_last_error());
+    }
 
     // Flags: types, then fast-path hints, fluid count and edge-cell list.
     k_flag_types<<<grid_for((uint64_t)h->ntot, 256), 256, 0, h->stream>>>(h->flags, d->nx, d->ny, d->nz,
@@ -1148,6 +1190,34 @@ int lbm_invariants(lbm_handle* h, double* mass, double* kinetic_energy)
 {
     if (!h || !mass || !kinetic_energy) return fail(LBM_EINVAL, "null argument");
     return invariants_raw(h, mass, kinetic_energy);
+}
+
+// The kernels of lbm_invariants, with the partial sums in the GPU's copy of
+// `scratch` (address looked up at creation) instead of the handle's buffer;
+// no allocation, and no wait when the result is a device pointer.
+int lbm_invariants_noalloc(lbm_handle* h, double* result)
+{
+    if (!h || !result) return fail(LBM_EINVAL, "null argument");
+    if (h->ntot > kNoAllocMaxCells)
+        return fail(LBM_EINVAL, "lbm_invariants_noalloc: " + std::to_string(h->ntot) +
+                                    " cells exceed its scratch maximum of 2^25 cells (use lbm_invariants)");
+    if (!h->scratch) return fail(LBM_EDEVICE, "lbm_invariants_noalloc: scratch address unknown");
+    Launch L = h->base(OP_INVARIANTS);
+    L.block = 256;
+    L.grid = (uint32_t)h->red_blocks;
+    L.aa_odd = pending_gather(h);
+    L.d0 = h->scratch;
+    int rc = run(h, L);
+    if (rc) return rc;
+    const bool host = h->d.ptr_kind == LBM_PTR_HOST;
+    double* res = host ? h->scratch + 2 * (size_t)h->red_blocks : result;
+    k_reduce_pairs<<<1, 256, 0, h->stream>>>(h->scratch, h->red_blocks, res);
+    HIP_TRY(hipGetLastError(), "kernel launch");
+    if (host) {
+        HIP_TRY(hipMemcpyAsync(result, res, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    }
+    return LBM_OK;
 }
 
 int lbm_neighbor_index(lbm_handle* h, const int64_t* cells, int n, int64_t* out)

@@ -67,7 +67,7 @@ SYMBOLS = [
     "lbm_desc_default", "lbm_required_bytes", "lbm_create", "lbm_create_ex", "lbm_destroy",
     "lbm_init_equilibrium", "lbm_set_geometry", "lbm_step", "lbm_macroscopic", "lbm_get_populations", "lbm_get_populations_at",
     "lbm_set_populations",
-    "lbm_get_flags", "lbm_invariants", "lbm_neighbor_index", "lbm_get_info", "lbm_lattice", "lbm_device_copy",
+    "lbm_get_flags", "lbm_invariants", "lbm_invariants_noalloc", "lbm_neighbor_index", "lbm_get_info", "lbm_lattice", "lbm_device_copy",
     "lbm_sync", "lbm_stream_copy",
     "lbm_last_error", "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_sequential",
     "lbm_batch_macroscopic", "lbm_batch_get_populations", "lbm_batch_invariants", "lbm_batch_info",
@@ -104,6 +104,7 @@ def lib() -> ctypes.CDLL:
     L.lbm_set_populations.argtypes = [P, P]
     L.lbm_get_flags.argtypes = [P, P]
     L.lbm_invariants.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D)]
+    L.lbm_invariants_noalloc.argtypes = [P, P]
     L.lbm_neighbor_index.argtypes = [P, P, I, P]
     L.lbm_get_info.argtypes = [P, ctypes.POINTER(Info)]
     L.lbm_lattice.argtypes = [I, P, P, P]
