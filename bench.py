@@ -213,35 +213,52 @@ def run_taylor_green(steps, scheme):
             "scheme": scheme, "steps": steps, "analytic_exp_minus_3nuk2t": math.exp(-3 * W.TGV_NU * k * k * steps), **out}
 
 
-def run_ensemble(steps, seq_steps):
+def run_ensemble(steps, seq_steps, scheme="aa", warmup=100):
     """512 independent D3Q19 TRT cavities (edge U{16..64}, Re U[100,1000],
-    u_lid 0.03), FP32-shifted AA: one launch per step replayed from a HIP
-    graph vs one launch per cavity per step."""
+    u_lid 0.03), FP32-shifted storage under one scheme: one step is one fast
+    kernel over the (cavity, tile) table plus the edge-cell kernel on a second
+    stream, replayed from a HIP graph with the autotuned launch shape, vs one
+    launch per cavity per step. Timed with events on the batch's stream."""
     import torch
     from paper_2010_11751_amd import lbm, workloads as W
     members = W.ensemble(512)
     cav = [lbm.Cavity(m.n, m.omega, m.u_lid) for m in members]
     res = {}
+    stream = torch.cuda.Stream()  # the batch runs on this stream (the null stream would get a private one)
     for mode in ("graph", "sequential"):
-        b = lbm.Batch(cav, scheme="aa", collision="trt", dtype="f32", use_graph=(mode == "graph"),
-                      graph_steps=100, autotune=(mode == "graph"))
+        with torch.cuda.stream(stream):
+            b = lbm.Batch(cav, scheme=scheme, collision="trt", dtype="f32", use_graph=(mode == "graph"),
+                          graph_steps=100, autotune=(mode == "graph"))
         cells, fluid, blk = b.info()
+        shape = b.launch_shape()
         n = steps if mode == "graph" else seq_steps
-        warm = 100 if mode == "graph" else 2
-        (b.step if mode == "graph" else b.step_sequential)(warm)
+        run = b.step if mode == "graph" else b.step_sequential
+        run(warmup if mode == "graph" else 2)
         b.sync()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
-        (b.step if mode == "graph" else b.step_sequential)(n)
+        e0.record(stream)
+        run(n)
+        e1.record(stream)
         b.sync()
-        dt = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / n
         masses, _ = b.invariants()
-        res[mode] = {"mlups": round(fluid * n / dt / 1e6, 1), "steps": n, "block_size": blk,
+        gbs = fluid * 153 / (ms * 1e-3) / 1e9
+        res[mode] = {"mlups": round(fluid / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 5), "steps": n,
+                     "wall_s": round(wall, 3), "hbm_gbs_algorithmic": round(gbs, 1),
+                     "roofline_frac": round(gbs / PEAK_HBM_GBS, 4),
                      "nonfinite_cavities": int(sum(1 for m in masses if m != m))}
+        if mode == "graph":
+            res[mode]["launch_shape"] = {"block": shape[0], "cells_per_thread": shape[1],
+                                         "waves_per_simd": shape[2], "xcd_split": shape[3], "edge_cells": shape[4]}
         b.close()
         del b
         torch.cuda.empty_cache()
-    return {"workload": "512 D3Q19 TRT cavities, L~U{16..64}, Re~U[100,1000], u_lid=0.03, FP32-shifted AA",
-            "cells": int(cells), "fluid_cells": int(fluid), **res,
+    return {"workload": f"512 D3Q19 TRT cavities, L~U{{16..64}}, Re~U[100,1000], u_lid=0.03, FP32-shifted {scheme}",
+            "scheme": scheme, "cells": int(cells), "fluid_cells": int(fluid), "bytes_per_update": 153, **res,
             "speedup_graph_vs_sequential": round(res["graph"]["mlups"] / res["sequential"]["mlups"], 2)}
 
 
@@ -409,6 +426,8 @@ def main():
                     help="only the periodic 256^3 Taylor-Green workload (2Pop pull and AA; FP64 / FP32 / FP16)")
     ap.add_argument("--validation", action="store_true",
                     help="only the cavity self-convergence study (Re 100, M = 32 / 64 / 128)")
+    ap.add_argument("--ensemble", action="store_true",
+                    help="only the 512-cavity ensemble (AA and 2Pop pull; --steps graph steps, --warmup warm-up steps)")
     ap.add_argument("--traffic", action="store_true",
                     help="short run for hardware byte counters: one 1 GiB device copy, then 4 BGK steps of "
                          "the 256^3 cavity each for AA FP64 / FP32-shifted, 2Pop FP64, swap FP64 and 2Pop pull "
@@ -434,6 +453,11 @@ def main():
         return
     if args.validation:
         validation()
+        return
+    if args.ensemble:
+        seq = max(2, min(100, args.steps // 10))
+        print(json.dumps({"ensemble_512": run_ensemble(args.steps, seq, "aa", args.warmup),
+                          "ensemble_512_pull": run_ensemble(args.steps, seq, HEAD_SCHEME, args.warmup)}), flush=True)
         return
     if args.taylor_green:
         print(json.dumps({"taylor_green_256": run_taylor_green(args.steps, HEAD_SCHEME),
@@ -482,6 +506,9 @@ def main():
         print("# taylor-green done", file=sys.stderr, flush=True)
         workloads["ensemble_512"] = run_ensemble(1000, 100)
         print(f"# ensemble: {workloads['ensemble_512']['graph']['mlups']} MLUPS (graph)", file=sys.stderr, flush=True)
+        workloads["ensemble_512_pull"] = run_ensemble(1000, 100, HEAD_SCHEME)
+        print(f"# ensemble {HEAD_SCHEME}: {workloads['ensemble_512_pull']['graph']['mlups']} MLUPS (graph)",
+              file=sys.stderr, flush=True)
     copy_gbs = copy_ceiling_gbs()
     print(f"# copy kernel: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     streams_gbs = stream_copy_ceiling(cav)
@@ -576,11 +603,14 @@ def write_records(path, out, heads, copy_gbs):
             recs.append({"workload": "taylor_green_256", "scheme": w[key]["scheme"], "collision": "bgk", "dtype": dtype,
                          "layout": "soa", "mlups_fluid": r["mlups"], "gbs_algorithmic": r["hbm_gbs"],
                          "velocity_rel_l2_vs_f64": r.get("velocity_rel_l2_vs_f64")})
-    if "ensemble_512" in w:
+    for key in ("ensemble_512", "ensemble_512_pull"):
+        if key not in w:
+            continue
         for mode in ("graph", "sequential"):
-            r = w["ensemble_512"][mode]
-            recs.append({"workload": "ensemble_512", "scheme": "aa", "collision": "trt", "dtype": "f32",
-                         "layout": "soa", "mode": mode, "mlups_fluid": r["mlups"]})
+            r = w[key][mode]
+            recs.append({"workload": "ensemble_512", "scheme": w[key]["scheme"], "collision": "trt", "dtype": "f32",
+                         "layout": "soa", "mode": mode, "mlups_fluid": r["mlups"],
+                         "gbs_algorithmic": r["hbm_gbs_algorithmic"]})
     with open(path, "a") as f:
         for r in recs:
             g = r.get("gbs_algorithmic")

@@ -301,18 +301,35 @@ typedef struct lbm_cavity_desc {
 typedef struct lbm_batch_opts {
     int use_graph;        /* capture the step loop in a HIP graph              */
     int graph_steps;      /* steps per captured graph (even, default 100)      */
-    int autotune;         /* time candidate block sizes on first step          */
+    int autotune;         /* time candidate launch shapes at creation: block
+                             size x cells per thread, then the residency cap */
     int block_size;       /* fixed block size when autotune = 0 (0 = 256)      */
     void *stream;         /* hipStream_t; NULL = a library-owned stream        */
-    const char *autotune_cache; /* text file of tuned block sizes, one "key block"
-                             line per ensemble (key: GPU arch, scheme,
-                             collision, dtype, cavity sizes); a hit skips the
-                             trial runs, a miss appends the result; NULL: none */
+    const char *autotune_cache; /* text file of tuned launch shapes, one line
+                             "key block cells_per_thread waves_per_simd xcd" per
+                             ensemble (key: GPU arch, scheme, collision,
+                             dtype, cavity sizes); a hit skips the trial runs,
+                             a miss appends the result; NULL: none          */
+    int cells_per_thread; /* fixed runs of block_size cells per block of the
+                             fast kernel when autotune = 0: 1, 2 or 4 (0 = 1) */
+    int waves_per_simd;   /* fixed residency cap of the fast kernel when
+                             autotune = 0: -1 = the storage type's default,
+                             0 = none, 1..8 = that many waves              */
+    int xcd_split;        /* fixed tile order when autotune = 0: 0 or 1 =
+                             the table dealt to the eight XCDs in contiguous
+                             parts (one cavity's tiles share an L2), 2 =
+                             blocks in table order                          */
 } lbm_batch_opts;
 
-/* Create count cavities (FP64 or shifted FP32/FP16, D3Q19, 2Pop or AA
- * (swap and 2Pop pull: LBM_EUNSUPPORTED), any collision; omega_bulk = omega and, for the moment-space models,
- * omega3 = omega4 = 1). opts may be NULL. Initial state: rho = 1, u = 0. */
+/* Create count cavities (FP64 or shifted FP32/FP16, D3Q19, any collision;
+ * omega_bulk = omega and, for the moment-space models, omega3 = omega4 = 1)
+ * under the 2Pop, AA or 2Pop pull scheme (swap: LBM_EUNSUPPORTED). opts may
+ * be NULL (then: no graph, no autotuning, blocks of 256, one run per block,
+ * default residency). Initial state: rho = 1, u = 0. A step is one kernel
+ * over a (cavity, tile) table that skips each cavity's x = 0 and x = nx-1
+ * wall layers (tiles of the largest cavities first), and, for the kinds that
+ * reach neighbours, one kernel over the fluid cells next to two or more
+ * walls, on a second stream of the library. */
 lbm_batch *lbm_batch_create(int count, const lbm_cavity_desc *d, int scheme, int collision,
                             int storage_dtype, const lbm_batch_opts *opts);
 int lbm_batch_step(lbm_batch *b, int n);
@@ -324,6 +341,12 @@ int lbm_batch_get_populations(lbm_batch *b, int idx, double *f);
 int lbm_batch_invariants(lbm_batch *b, double *mass, double *kinetic_energy);
 /* Total cells, fluid cells and block size in use (host pointers). */
 int lbm_batch_info(lbm_batch *b, int64_t *cells, int64_t *fluid_cells, int *block_size);
+/* Launch shape of the fast kernel in use (block size, cells per thread,
+ * residency cap: -1 default, 0 none; XCD split 1 on, 0 off) and the number
+ * of fluid cells next to two or more walls (host pointers, each may be
+ * NULL). */
+int lbm_batch_launch_shape(lbm_batch *b, int *block_size, int *cells_per_thread, int *waves_per_simd,
+                           int *xcd_split, int64_t *edge_cells);
 int lbm_batch_sync(lbm_batch *b);
 void lbm_batch_destroy(lbm_batch *b);
 

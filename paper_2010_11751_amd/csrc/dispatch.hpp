@@ -71,14 +71,44 @@ hipError_t launch_slow_kind(const Launch& L, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int Q, int MODEL, class ST, int LAYOUT>
+template <int Q, int MODEL, class ST>
 hipError_t launch_batch_kind(const Launch& L, hipStream_t s)
 {
     const dim3 g(L.grid), b(L.block);
+    const uint32_t lds = L.lds;
+    if (L.box) {
+        switch (L.kind) {
+        case KIND_AA_EVEN: k_step_batch_box<Q, MODEL, ST, KIND_AA_EVEN><<<g, b, lds, s>>>(L.cav, L.tiles, L.cpt, L.xcd); break;
+        case KIND_AA_ODD: k_step_batch_box<Q, MODEL, ST, KIND_AA_ODD><<<g, b, lds, s>>>(L.cav, L.tiles, L.cpt, L.xcd); break;
+        case KIND_PULL: k_step_batch_box<Q, MODEL, ST, KIND_PULL><<<g, b, lds, s>>>(L.cav, L.tiles, L.cpt, L.xcd); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (L.kind) {
-    case KIND_2POP: k_step_batch<Q, MODEL, ST, LAYOUT, KIND_2POP><<<g, b, 0, s>>>(L.cav, L.tiles); break;
-    case KIND_AA_EVEN: k_step_batch<Q, MODEL, ST, LAYOUT, KIND_AA_EVEN><<<g, b, 0, s>>>(L.cav, L.tiles); break;
-    case KIND_AA_ODD: k_step_batch<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, 0, s>>>(L.cav, L.tiles); break;
+    case KIND_2POP: k_step_batch<Q, MODEL, ST, KIND_2POP><<<g, b, lds, s>>>(L.cav, L.tiles, L.cpt, L.xcd); break;
+    case KIND_AA_EVEN: k_step_batch<Q, MODEL, ST, KIND_AA_EVEN><<<g, b, lds, s>>>(L.cav, L.tiles, L.cpt, L.xcd); break;
+    case KIND_AA_ODD: k_step_batch<Q, MODEL, ST, KIND_AA_ODD><<<g, b, lds, s>>>(L.cav, L.tiles, L.cpt, L.xcd); break;
+    case KIND_PULL: k_step_batch<Q, MODEL, ST, KIND_PULL><<<g, b, lds, s>>>(L.cav, L.tiles, L.cpt, L.xcd); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int Q, int MODEL, class ST>
+hipError_t launch_batch_slow_kind(const Launch& L, hipStream_t s)
+{
+    const dim3 g(L.grid), b(256);
+    switch (L.kind) {
+    case KIND_2POP:
+        k_step_batch_slow<Q, MODEL, ST, KIND_2POP><<<g, b, 0, s>>>(L.cav, L.wave_cav, L.slow_list, L.n_slow);
+        break;
+    case KIND_AA_ODD:
+        k_step_batch_slow<Q, MODEL, ST, KIND_AA_ODD><<<g, b, 0, s>>>(L.cav, L.wave_cav, L.slow_list, L.n_slow);
+        break;
+    case KIND_PULL:
+        k_step_batch_slow<Q, MODEL, ST, KIND_PULL><<<g, b, 0, s>>>(L.cav, L.wave_cav, L.slow_list, L.n_slow);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -95,7 +125,10 @@ hipError_t launch_model(const Launch& L, hipStream_t s)
         if constexpr (Q == 19 && LAYOUT == LAYOUT_SOA) return launch_all_kind<Q, MODEL, ST, LAYOUT>(L, s);
         else return hipErrorInvalidValue;
     case OP_STEP_BATCH:
-        if constexpr (Q == 19 && LAYOUT == LAYOUT_SOA) return launch_batch_kind<Q, MODEL, ST, LAYOUT>(L, s);
+        if constexpr (Q == 19 && LAYOUT == LAYOUT_SOA) return launch_batch_kind<Q, MODEL, ST>(L, s);
+        else return hipErrorInvalidValue;
+    case OP_STEP_BATCH_SLOW:
+        if constexpr (Q == 19 && LAYOUT == LAYOUT_SOA) return launch_batch_slow_kind<Q, MODEL, ST>(L, s);
         else return hipErrorInvalidValue;
     case OP_INIT: k_init<Q, MODEL, ST, LAYOUT><<<g, b, 0, s>>>(L.F, L.init); break;
     default: return hipErrorInvalidValue;

@@ -66,6 +66,17 @@ struct StoreF16 {
     static constexpr bool shifted = true;
 };
 
+// Momentum-exchange terms of a lid cell of the built-in geometries,
+// w_k = -6 t_k c_k . u_lid with rho_w = 1 (Eq. storage2), computed once on
+// the host and rounded to the storage type: every kernel that stores a lid
+// cell's terms (initialisation, and the step kernels whose wall lanes write
+// them back) takes them from this table, so they are the same bits wherever
+// they are written, and the step kernels do no FP64 arithmetic for them.
+struct LidTerms {
+    double d[27];  // FP64 storage
+    float f[27];   // FP32 and FP16 storage (the FP16 value held exactly in a float)
+};
+
 // One lattice as the kernels see it.
 struct Field {
     void* pop;
@@ -76,7 +87,7 @@ struct Field {
     int nx, ny, nz;
     int reverse;           // visit cells in reverse block / list order (traversal-order tests)
     int custom_walls;      // wall terms set per cell by the caller (else: from type and lid)
-    double lid[3];         // lid velocity of the built-in geometries
+    LidTerms lid;          // terms of lid cells (built-in geometries)
 };
 
 // Largest block of the step kernels: the moment-space models (model >= 4)
@@ -143,7 +154,6 @@ struct RelaxD {
 struct InitArgs {
     const double* rho;     // device, may be null
     const double* u;       // device [3][ntot], may be null
-    double lid[3];
     const double* wall_u;    // device [3][ntot]: per-cell wall velocity, may be null
     const double* wall_rho;  // device [ntot]: per-cell wall density, may be null
     int keep_walls;          // leave the stored terms of wall cells untouched
@@ -157,7 +167,7 @@ struct BatchCavity {
 // A launch request handled by the kernel translation unit of (Q, storage).
 enum Op { OP_STEP = 0, OP_GET = 1, OP_MACRO = 2, OP_SET = 3, OP_INIT = 4, OP_INVARIANTS = 5, OP_NEIGHBORS = 6,
           OP_STEP_BATCH = 7, OP_GET_CELLS = 8, OP_STEP_SLOW = 9,
-          OP_STEP_ALL = 10 };
+          OP_STEP_ALL = 10, OP_STEP_BATCH_SLOW = 11 };
 
 struct Launch {
     int op;
@@ -174,12 +184,21 @@ struct Launch {
     const int64_t* cells;  // NEIGHBORS
     int64_t* idx_out;
     int n;
-    const BatchCavity* cav;  // STEP_BATCH
-    const uint32_t* tiles;
+    const BatchCavity* cav;  // STEP_BATCH, STEP_BATCH_SLOW
+    const uint32_t* tiles;   // STEP_BATCH: (cavity << 16 | tile) per block
+    uint32_t cpt;            // STEP_BATCH: runs of blockDim cells per tile
+    int box;                 // STEP_BATCH: cells decided by position (box cavities), no edge part
+    uint32_t xcd;            // STEP_BATCH: deal the tile table to the eight XCDs in contiguous parts
+                             //   (grid a multiple of eight)
+    const uint32_t* wave_cav;  // STEP_BATCH_SLOW: cavity of each wave of the edge-cell list
     const uint32_t* slow_list;  // STEP_SLOW: fluid cells off the fast path
     uint32_t n_slow;
     uint32_t lds;          // STEP: dynamic LDS bytes per block (caps blocks per CU)
 };
+
+// Lid terms of a lattice of Q velocities stored in elements of elem_bytes
+// (8, 4 or 2) for lid velocity u (host).
+LidTerms lid_terms(int q, int elem_bytes, const double u[3]);
 
 hipError_t launch_q19_f64(const Launch& L, hipStream_t s);
 hipError_t launch_q19_f32(const Launch& L, hipStream_t s);

@@ -139,6 +139,29 @@ __device__ __forceinline__ Relax<R> relax_of(const RelaxD& p)
     return Relax<R>{R(p.omega), R(p.omega_m), R(p.omega_b), R(p.omega3), R(p.omega4)};
 }
 
+// Stored terms of a wall cell of the built-in geometries: the lid's terms on
+// lid cells (from the host's table, in the storage type), zero on the walls
+// at rest.
+template <int Q, class ST, int K>
+__device__ __forceinline__ real_t<ST> builtin_wall_term(const Field& F, uint8_t type)
+{
+    if (type != FL_LID) return real_t<ST>(0);
+    if constexpr (sizeof(typename ST::T) == 8) return F.lid.d[K];
+    else return F.lid.f[K];
+}
+
+// A wall lane of a step kernel writes its own (unchanged) terms back. No
+// fluid cell writes a wall cell's slots in the push-type steps, so without
+// this every cache line holding wall slots would be written only in part,
+// which HBM turns into a read-modify-write. Built-in geometries only: caller
+// walls hold per-cell terms that the lane does not have.
+template <int Q, class ST, int LAYOUT>
+__device__ __forceinline__ void store_wall_terms(const Field& F, void* base, uint32_t i, uint8_t fl)
+{
+    const Acc<ST, LAYOUT, Q, true> a{(typename ST::T*)base, F.stride};
+    static_for<0, Q>([&](auto K) { a.st(i, K, builtin_wall_term<Q, ST, K>(F, fl & FL_TYPE)); });
+}
+
 // Loads never wait for the flag byte: every lane issues its population loads
 // at once (lanes of wall cells read harmless values from inside the
 // allocation), collides, and only the stores and the bounce-back gather of
@@ -162,12 +185,6 @@ __device__ __forceinline__ void issue_all(R (&g)[Q])
 // pass (used by the batched ensemble). Each cell touches its own set of
 // memory locations, so the split does not change any result (Sec. 2.3).
 enum Part { PART_ALL = 0, PART_FAST = 1, PART_SLOW = 2 };
-
-template <int PART>
-__device__ __forceinline__ bool take_fast(uint8_t fl)
-{
-    return (fl & (FL_TYPE | FL_SLOW)) == FL_FLUID;
-}
 
 // Wall-plane cells stay on the fast path: their non-fluid neighbours are
 // exactly the nine on one side of the cell, the side with normal axis a and
@@ -232,7 +249,10 @@ __device__ __forceinline__ void cell_2pop(const Field& F, const Relax<real_t<ST>
     if constexpr (PART == PART_SLOW) {
         push_2pop_slow<Q, ST, LAYOUT>(F, i, fl, g);
     } else {
-        if ((fl & FL_TYPE) != FL_FLUID) return;
+        if ((fl & FL_TYPE) != FL_FLUID) {
+            if (!F.custom_walls) store_wall_terms<Q, ST, LAYOUT>(F, F.out, i, fl);
+            return;
+        }
         if (!(fl & FL_SLOW)) {
             static_for<0, Q>([&](auto K) {
                 constexpr int k = K;
@@ -426,7 +446,11 @@ __device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<S
             });
         }
         collide<Q, MODEL, ST::shifted>(g, p);
-        if (!take_fast<PART>(fl) && !(ZWRAP && (fl & FL_ZWRAP))) return;
+        if ((fl & FL_TYPE) != FL_FLUID) {
+            if (!F.custom_walls) store_wall_terms<Q, ST, LAYOUT>(F, F.pop, i, fl);
+            return;
+        }
+        if ((fl & FL_SLOW) && !(ZWRAP && (fl & FL_ZWRAP))) return;  // written by the slow part
         static_for<0, Q>([&](auto K) {
             constexpr int k = K;
             if (!wall_to<Q, k>(fl)) {
@@ -438,17 +462,6 @@ __device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<S
             }
         });
     }
-}
-
-// Momentum-exchange term of a wall cell, w_k = -6 t_k c_k . u_w with rho_w = 1
-// (Eq. momentum-exchange, Eq. storage2); u_w = lid velocity on LID cells.
-template <int Q, int K>
-__device__ __forceinline__ double wall_term(uint8_t type, const double (&lid)[3])
-{
-    using S = L<Q>;
-    if (type != FL_LID) return 0.0;
-    const double cu = S::cx(K) * lid[0] + S::cy(K) * lid[1] + S::cz(K) * lid[2];
-    return -6.0 * S::t(K) * cu;
 }
 
 // Two-population scheme in pull form, beside the push form of Table 1
@@ -535,10 +548,9 @@ __device__ __forceinline__ void cell_pull(const Field& F, const Relax<real_t<ST>
             // built-in geometries the terms follow from the cell type and the
             // lid velocity, as at initialisation, so no reload is needed.
             if (!F.custom_walls) {
-                const double lid[3] = {F.lid[0], F.lid[1], F.lid[2]};
                 static_for<0, Q>([&](auto K) {
                     constexpr int k = K;
-                    g[k] = R(wall_term<Q, S::opp(k)>(fl & FL_TYPE, lid));
+                    g[k] = builtin_wall_term<Q, ST, S::opp(k)>(F, fl & FL_TYPE);
                 });
             } else {
                 static_for<0, Q>([&](auto K) {
@@ -696,17 +708,213 @@ __global__ void __launch_bounds__(256) k_step_slow(Field F, RelaxD pd, const uin
 }
 
 // ---------------------------------------------------------------------------
-// Batched ensemble: one launch over a table of (cavity, first cell) tiles.
-template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
-__global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) k_step_batch(const BatchCavity* __restrict__ cav,
-                                                     const uint32_t* __restrict__ tiles)
+// Box cavities of the built-in geometry, with every decision taken from the
+// cell's position instead of its flag byte: a cell is fluid iff
+// 1 <= x <= nx-2 (and so for y, z), its neighbour x +- c_k is a wall iff it
+// leaves that range, and a wall cell is a lid cell iff it lies in the layer
+// z = nz-1. Each direction then costs one load and one store whose address
+// is chosen per lane (neighbour slot, or the cell's own slot across a wall)
+// and the wall terms come from the lid table, so walls, faces, edges and
+// corners all stay on one branch-free path, with no flag traffic and no
+// second gather round. Used by the ensemble, whose members are such
+// cavities; ntot < 2^24 (exact float quotients below).
+
+// Lid term w_J of the table in the storage type.
+template <class ST, int J>
+__device__ __forceinline__ real_t<ST> lid_value(const Field& F)
 {
-    const uint32_t t = tiles[blockIdx.x];
-    const uint32_t c = t >> 16;  // cavity
+    if constexpr (sizeof(typename ST::T) == 8) return F.lid.d[J];
+    else return F.lid.f[J];
+}
+
+struct BoxPos {
+    // lo[a]: coordinate a is 1; hi[a]: it is n_a - 2 (both for n_a = 3);
+    // top: the cell lies in the lid layer z = nz - 1.
+    bool fluid, top, lo[3], hi[3];
+};
+
+// floor(n / d) for n < 2^24 and d >= 1: the float quotient is within one of
+// the true one, and one correction step fixes it.
+__device__ __forceinline__ uint32_t udiv24(uint32_t n, uint32_t d, float rcp)
+{
+    uint32_t q = (uint32_t)((float)n * rcp);
+    const int32_t r = (int32_t)(n - q * d);
+    if (r < 0) --q;
+    else if (r >= (int32_t)d) ++q;
+    return q;
+}
+
+__device__ __forceinline__ BoxPos box_pos(const Field& F, uint32_t i, float rcp_nz, float rcp_ny)
+{
+    const uint32_t row = udiv24(i, (uint32_t)F.nz, rcp_nz);
+    const int z = (int)(i - row * (uint32_t)F.nz);
+    const uint32_t x = udiv24(row, (uint32_t)F.ny, rcp_ny);
+    const int y = (int)(row - x * (uint32_t)F.ny);
+    const int c[3] = {(int)x, y, z}, n[3] = {F.nx, F.ny, F.nz};
+    BoxPos p;
+    p.fluid = true;
+    for (int a = 0; a < 3; ++a) {
+        p.fluid = p.fluid && c[a] >= 1 && c[a] <= n[a] - 2;
+        p.lo[a] = c[a] == 1;
+        p.hi[a] = c[a] == n[a] - 2;
+    }
+    p.top = z == F.nz - 1;
+    return p;
+}
+
+// Fluid cell: x + s*c_k is a wall.
+template <int Q, int K, int SIGN>
+__device__ __forceinline__ bool box_wall(const BoxPos& p)
+{
+    bool w = false;
+    static_for<0, 3>([&](auto A) {
+        constexpr int a = A;
+        constexpr int c = SIGN * L<Q>::c(K, a);
+        if constexpr (c > 0) w = w || p.hi[a];
+        else if constexpr (c < 0) w = w || p.lo[a];
+    });
+    return w;
+}
+
+// Fluid cell whose neighbour x + s*c_k is a wall: the stored term of that
+// wall cell in slot J, a lid term iff the wall lies in the layer z = nz - 1.
+template <int Q, int K, int SIGN, class ST, int J>
+__device__ __forceinline__ real_t<ST> box_wall_term(const Field& F, const BoxPos& p)
+{
+    if constexpr (SIGN * L<Q>::cz(K) > 0) return p.hi[2] ? lid_value<ST, J>(F) : real_t<ST>(0);
+    else return real_t<ST>(0);
+}
+
+// One step of one cell of a box cavity. AA even: local collide, slot kbar.
+// AA odd: gather f_k from pop_kbar(x - c_k), or pop_k(x) + w_kbar(x - c_k)
+// across a wall; collide; push f_out_k to pop_k(x + c_k), or pop_kbar(x) <-
+// f_out_k + w_k(x + c_k) across a wall (Table 1, row AA). Pull: the same
+// gather from pop, then out_kbar(x) <- f_out_k. Wall lanes load nothing and
+// write their own terms (AA: into pop; pull: into out), which keeps every
+// line written whole. Every lane of a wave runs the same instructions: one
+// load per direction (fluid lanes only) and one store per direction, whose
+// byte offset from the array base and whose value are chosen per lane. The
+// sums are the ones the flag-driven kernels form, operand for operand, so
+// the results are the same bits.
+template <int Q, int MODEL, class ST, int KIND>
+__device__ __forceinline__ void box_cell(const Field& F, const Relax<real_t<ST>>& rp, uint32_t i, const BoxPos& p)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    using T = typename ST::T;
+    constexpr uint32_t sz = sizeof(T);
+    char* const src = (char*)F.pop;
+    char* const dst = (char*)(KIND == KIND_PULL ? F.out : F.pop);
+    const uint32_t sb = (uint32_t)F.stride * sz;  // bytes between streams (< 2^32 / Q here)
+    const uint32_t ib = i * sz;
+    auto at = [&](char* base, uint32_t off) -> T* { return reinterpret_cast<T*>(base + off); };
+    R g[Q];
+    static_for<0, Q>([&](auto K) { g[K] = R(0); });
+    if (p.fluid) {
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            if constexpr (KIND == KIND_AA_EVEN || k == S::rest) {
+                g[k] = R(*at(src, k * sb + ib));
+            } else {  // pop_kbar(x - c_k), or pop_k(x) across a wall
+                const uint32_t nb = S::opp(k) * sb + ib + (uint32_t)(offset<Q, k, -1>(F) * (int32_t)sz);
+                g[k] = R(*at(src, box_wall<Q, k, -1>(p) ? k * sb + ib : nb));
+            }
+        });
+        if constexpr (KIND != KIND_AA_EVEN) {
+            static_for<0, Q>([&](auto K) {
+                constexpr int k = K;
+                if constexpr (k != S::rest)
+                    if (box_wall<Q, k, -1>(p)) g[k] += box_wall_term<Q, k, -1, ST, S::opp(k)>(F, p);
+            });
+        }
+    }
+    collide<Q, MODEL, ST::shifted>(g, rp);
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        const R wv = p.top ? lid_value<ST, S::opp(k)>(F) : R(0);  // a wall lane's term in slot kbar
+        if constexpr (KIND == KIND_AA_EVEN || KIND == KIND_PULL) {
+            *at(dst, S::opp(k) * sb + ib) = T(p.fluid ? g[k] : wv);
+        } else if constexpr (k == S::rest) {
+            *at(dst, k * sb + ib) = T(p.fluid ? g[k] : wv);
+        } else {
+            // Fluid: pop_k(x + c_k) <- f_out_k, or pop_kbar(x) <- f_out_k +
+            // w_k(x + c_k) across a wall. Wall lane: its own slot kbar.
+            const bool w = box_wall<Q, k, 1>(p);
+            const uint32_t nb = k * sb + ib + (uint32_t)(offset<Q, k, 1>(F) * (int32_t)sz);
+            const uint32_t off = p.fluid && !w ? nb : S::opp(k) * sb + ib;
+            const R v = !p.fluid ? wv : (w ? g[k] + box_wall_term<Q, k, 1, ST, k>(F, p) : g[k]);
+            *at(dst, off) = T(v);
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Batched ensemble, fast part: one launch over a table of (cavity, tile)
+// entries, one block per entry. A tile is `cpt` consecutive runs of
+// blockDim cells of one cavity, counted from the first cell of the layer
+// x = 1: the layers x = 0 and x = nx - 1 are walls that no step needs to
+// touch (their slots are whole runs of cache lines, so leaving them alone
+// costs no partial-line writes). Fluid cells next to two or more walls
+// (edges and corners) are left to the edge-cell kernel below; wall lanes
+// write their terms back.
+template <int Q, int MODEL, class ST, int KIND>
+__global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T)))
+    LBM_STEP_ATTR(Q, ST, KIND) k_step_batch(const BatchCavity* __restrict__ cav, const uint32_t* __restrict__ tiles,
+                                            uint32_t cpt, uint32_t xcd)
+{
+    const uint32_t b = xcd ? (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    const uint32_t t = tiles[b];
+    if (t == 0xffffffffu) return;  // padding of the table to a multiple of eight
+    const BatchCavity& B = cav[t >> 16];
+    const uint32_t plane = (uint32_t)B.F.ny * (uint32_t)B.F.nz;
+    const uint32_t end = B.F.ntot - plane;
+    uint32_t i = plane + (t & 0xffffu) * blockDim.x * cpt + threadIdx.x;
+    const Relax<real_t<ST>> p = relax_of<real_t<ST>>(B.relax);
+    for (uint32_t r = 0; r < cpt && i < end; ++r, i += blockDim.x)
+        cell_step<Q, MODEL, ST, LAYOUT_SOA, KIND, PART_FAST>(B.F, p, i);
+}
+
+// Batched ensemble of box cavities, every cell on the position-driven path
+// (AA and pull kinds; cavities of fewer than 2^24 cells): the same tiles as
+// above, no edge-cell kernel.
+template <int Q, int MODEL, class ST, int KIND>
+__global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T)))
+    LBM_STEP_ATTR(Q, ST, KIND) k_step_batch_box(const BatchCavity* __restrict__ cav,
+                                                const uint32_t* __restrict__ tiles, uint32_t cpt, uint32_t xcd)
+{
+    // xcd: the table is dealt in eight contiguous parts, one per XCD (blocks
+    // go to the XCDs in turn), so that the tiles of one cavity, and the
+    // neighbours they share, stay in one XCD's L2.
+    const uint32_t b = xcd ? (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    const uint32_t t = tiles[b];
+    if (t == 0xffffffffu) return;  // padding of the table to a multiple of eight
+    const BatchCavity& B = cav[t >> 16];
+    const uint32_t plane = (uint32_t)B.F.ny * (uint32_t)B.F.nz;
+    const uint32_t end = B.F.ntot - plane;
+    uint32_t i = plane + (t & 0xffffu) * blockDim.x * cpt + threadIdx.x;
+    const float rz = 1.0f / (float)B.F.nz, ry = 1.0f / (float)B.F.ny;
+    const Relax<real_t<ST>> p = relax_of<real_t<ST>>(B.relax);
+    for (uint32_t r = 0; r < cpt && i < end; ++r, i += blockDim.x)
+        box_cell<Q, MODEL, ST, KIND>(B.F, p, i, box_pos(B.F, i, rz, ry));
+}
+
+// Batched ensemble, edge part: the listed fluid cells off the fast path,
+// grouped by cavity so that each wave of 64 entries belongs to one cavity
+// (wave_cav; unused entries hold 0xffffffff), which keeps the cavity's
+// description in scalar registers.
+template <int Q, int MODEL, class ST, int KIND>
+__global__ void __launch_bounds__(256) k_step_batch_slow(const BatchCavity* __restrict__ cav,
+                                                        const uint32_t* __restrict__ wave_cav,
+                                                        const uint32_t* __restrict__ list, uint32_t n)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    // Every lane of a wave holds the same j >> 6.
+    const uint32_t c = __builtin_amdgcn_readfirstlane(wave_cav[j >> 6]);
+    const uint32_t i = list[j];
     const BatchCavity& B = cav[c];
-    const uint32_t i = (t & 0xffffu) * blockDim.x + threadIdx.x;
     if (i >= B.F.ntot) return;
-    cell_step<Q, MODEL, ST, LAYOUT, KIND, PART_ALL>(B.F, relax_of<real_t<ST>>(B.relax), i);
+    cell_step<Q, MODEL, ST, LAYOUT_SOA, KIND, PART_SLOW>(B.F, relax_of<real_t<ST>>(B.relax), i);
 }
 
 // ---------------------------------------------------------------------------
@@ -845,8 +1053,7 @@ __global__ void k_init(Field F, InitArgs ia)
                 g[k] = R(-6.0 * L<Q>::t(k) * rw * cu);
             });
         } else {
-            const double lid[3] = {ia.lid[0], ia.lid[1], ia.lid[2]};
-            static_for<0, Q>([&](auto K) { g[K] = R(wall_term<Q, K>(type, lid)); });
+            static_for<0, Q>([&](auto K) { g[K] = builtin_wall_term<Q, ST, K>(F, type); });
         }
     } else {
         const R rho = ia.rho ? R(ia.rho[i]) : R(1);

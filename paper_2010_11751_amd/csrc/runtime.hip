@@ -91,6 +91,29 @@ int64_t soa_halo(int ny, int nz)
     return (h + 255) / 256 * 256;
 }
 
+}  // namespace
+
+// The lid terms w_k = -6 t_k c_k . u (Eq. storage2, rho_w = 1) of the
+// built-in geometries, rounded to the storage type the way an FP32 value is
+// stored: FP64 as is, FP32 once, FP16 through FP32.
+LidTerms lbm::lid_terms(int q, int elem_bytes, const double u[3])
+{
+    LidTerms t{};
+    int32_t c[27][3];
+    double w[27];
+    int32_t opp[27];
+    lbm_lattice(q, &c[0][0], w, opp);
+    for (int k = 0; k < q; ++k) {
+        const double cu = c[k][0] * u[0] + c[k][1] * u[1] + c[k][2] * u[2];
+        const double v = -6.0 * w[k] * cu;
+        t.d[k] = v;
+        t.f[k] = elem_bytes == 2 ? (float)(_Float16)(float)v : (float)v;
+    }
+    return t;
+}
+
+namespace {
+
 double trt_omega_minus(double omega, double lambda)
 {
     return 1.0 / (0.5 + lambda / (1.0 / omega - 0.5));
@@ -366,7 +389,7 @@ struct lbm_handle {
         F.nz = d.nz;
         F.reverse = reverse_blocks ? 1 : 0;
         F.custom_walls = custom_walls ? 1 : 0;
-        for (int a = 0; a < 3; ++a) F.lid[a] = d.lid_velocity[a];
+        F.lid = lid_terms(q, (int)elem_bytes(d.storage_dtype), d.lid_velocity);
         return F;
     }
     Launch base(int op) const
@@ -473,7 +496,6 @@ static int init_state(lbm_handle* h, const double* rho, const double* u)
     Launch L = h->base(OP_INIT);
     L.init.rho = rho;
     L.init.u = u;
-    for (int a = 0; a < 3; ++a) L.init.lid[a] = h->d.lid_velocity[a];
     L.init.keep_walls = h->custom_walls ? 1 : 0;
     int rc = run(h, L);
     if (rc) return rc;
@@ -1044,7 +1066,6 @@ int lbm_set_geometry(lbm_handle* h, const uint8_t* type, const double* wall_velo
     Launch L = h->base(OP_INIT);
     L.init.wall_u = (const double*)du;
     L.init.wall_rho = (const double*)dr;
-    for (int a = 0; a < 3; ++a) L.init.lid[a] = d->lid_velocity[a];
     rc = run(h, L);
     if (rc) return rc;
     h->custom_walls = true;

@@ -60,7 +60,8 @@ class CavityDesc(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("use_graph", ctypes.c_int), ("graph_steps", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("block_size", ctypes.c_int), ("stream", ctypes.c_void_p), ("autotune_cache", ctypes.c_char_p)]
+                ("block_size", ctypes.c_int), ("stream", ctypes.c_void_p), ("autotune_cache", ctypes.c_char_p),
+                ("cells_per_thread", ctypes.c_int), ("waves_per_simd", ctypes.c_int), ("xcd_split", ctypes.c_int)]
 
 
 SYMBOLS = [
@@ -71,6 +72,7 @@ SYMBOLS = [
     "lbm_sync", "lbm_stream_copy",
     "lbm_last_error", "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_sequential",
     "lbm_batch_macroscopic", "lbm_batch_get_populations", "lbm_batch_invariants", "lbm_batch_info",
+    "lbm_batch_launch_shape",
     "lbm_batch_sync", "lbm_batch_destroy",
 ]
 
@@ -121,6 +123,7 @@ def lib() -> ctypes.CDLL:
     L.lbm_batch_get_populations.argtypes = [P, I, P]
     L.lbm_batch_invariants.argtypes = [P, P, P]
     L.lbm_batch_info.argtypes = [P, P, P, P]
+    L.lbm_batch_launch_shape.argtypes = [P, P, P, P, P, P]
     L.lbm_batch_sync.argtypes = [P]
     L.lbm_batch_destroy.argtypes = [P]
     L.lbm_batch_destroy.restype = None
@@ -337,7 +340,7 @@ class Batch:
 
     def __init__(self, cavities, scheme: str = "aa", collision: str = "trt", dtype: str = "f32",
                  use_graph: bool = True, graph_steps: int = 100, autotune: bool = False, block_size: int = 0,
-                 autotune_cache=None):
+                 autotune_cache=None, cells_per_thread: int = 0, waves_per_simd: int = -1, xcd_split: int = 1):
         arr = (CavityDesc * len(cavities))()
         self.sizes = []
         for j, c in enumerate(cavities):
@@ -346,7 +349,8 @@ class Batch:
             self.sizes.append(n ** 3)
         self.stream = torch.cuda.current_stream()
         opts = BatchOpts(int(use_graph), graph_steps, int(autotune), block_size, self.stream.cuda_stream,
-                         None if autotune_cache is None else str(autotune_cache).encode())
+                         None if autotune_cache is None else str(autotune_cache).encode(),
+                         cells_per_thread, waves_per_simd, 1 if xcd_split else 2)
         b = lib().lbm_batch_create(len(cavities), arr, SCHEMES[scheme], COLLISIONS[collision], DTYPES[dtype],
                                    ctypes.byref(opts))
         if not b:
@@ -397,3 +401,11 @@ class Batch:
         cells, fluid, blk = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
         check(lib().lbm_batch_info(self.b, ctypes.byref(cells), ctypes.byref(fluid), ctypes.byref(blk)))
         return cells.value, fluid.value, blk.value
+
+    def launch_shape(self):
+        """(block size, cells per thread, residency cap, XCD split, edge
+        cells) of the fast kernel in use."""
+        blk, cpt, waves, xcd, edge = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        check(lib().lbm_batch_launch_shape(self.b, ctypes.byref(blk), ctypes.byref(cpt), ctypes.byref(waves),
+                                           ctypes.byref(xcd), ctypes.byref(edge)))
+        return blk.value, cpt.value, waves.value, xcd.value, edge.value

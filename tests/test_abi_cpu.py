@@ -104,17 +104,33 @@ def test_null_handles_are_rejected(hiplib):
     L.lbm_batch_destroy(None)
 
 
-def test_batch_rejects_swap_and_pull_schemes(hiplib):
-    """The ensemble runs 2Pop or AA; swap and 2Pop pull are valid schemes it
-    does not support (checked before any device call)."""
+def test_batch_rejects_swap_and_unknown_schemes(hiplib):
+    """The ensemble runs 2Pop, AA or 2Pop pull; swap is a valid scheme it does
+    not support, 7 no scheme at all (checked before any device call)."""
     L = hiplib.lib()
     arr = (hiplib.CavityDesc * 1)()
     arr[0].nx = arr[0].ny = arr[0].nz = 16
     arr[0].omega, arr[0].u_lid, arr[0].trt_lambda = 1.8, 0.03, 0.25
-    for scheme in (hiplib.SCHEMES["swap"], hiplib.SCHEMES["2pop_pull"]):
-        assert not L.lbm_batch_create(1, arr, scheme, 1, 1, None)
-        assert "batch schemes" in hiplib.last_error()
+    assert not L.lbm_batch_create(1, arr, hiplib.SCHEMES["swap"], 1, 1, None)
+    assert "batch schemes" in hiplib.last_error()
     assert not L.lbm_batch_create(1, arr, 7, 1, 1, None)
+    assert "batch schemes" in hiplib.last_error()
+
+
+def test_batch_rejects_bad_launch_shapes(hiplib):
+    """Fixed launch shapes outside what the fast kernel supports are refused
+    before any device call."""
+    L = hiplib.lib()
+    arr = (hiplib.CavityDesc * 1)()
+    arr[0].nx = arr[0].ny = arr[0].nz = 16
+    arr[0].omega, arr[0].u_lid, arr[0].trt_lambda = 1.8, 0.03, 0.25
+    for kw, msg in (({"block_size": 96}, "block_size"), ({"cells_per_thread": 3}, "cells_per_thread"),
+                    ({"waves_per_simd": 9}, "waves_per_simd"), ({"xcd_split": 3}, "xcd_split")):
+        o = hiplib.BatchOpts()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        assert not L.lbm_batch_create(1, arr, hiplib.SCHEMES["aa"], 1, 1, ctypes.byref(o))
+        assert msg in hiplib.last_error()
 
 
 @pytest.mark.parametrize("scheme", (0, 3))

@@ -1,7 +1,8 @@
 """Batched ensemble on the GPU: each cavity of one batched launch equals the
-same cavity run alone (bit for bit, same storage type), graph replay equals
-the eager loop, per-cavity sequential launches equal the batched launch, and
-FP64 batches match the oracle."""
+same cavity run alone (bit for bit, same storage type) under every launch
+shape the autotuner can pick, graph replay equals the eager loop,
+per-cavity sequential launches equal the batched launch, and FP64 batches
+match the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -25,8 +26,21 @@ def make_batch(lbm, dtype, scheme="aa", coll="trt", **kw):
     return lbm.Batch(cav, scheme=scheme, collision=coll, dtype=dtype, **kw)
 
 
+SCHEMES = ("aa", "2pop", "2pop_pull")
+
+
+def edge_cells(n):
+    """Fluid cells of a cubic cavity of edge n (walls included) that lie next
+    to two or more walls: m = n - 2 fluid cells per edge, two boundary values
+    per axis (one when m = 1)."""
+    m = n - 2
+    if m <= 2:
+        return m ** 3
+    return 3 * 4 * (m - 2) + 8
+
+
 @pytest.mark.parametrize("dtype", ("f64", "f32", "f16"))
-@pytest.mark.parametrize("scheme", ("aa", "2pop"))
+@pytest.mark.parametrize("scheme", SCHEMES)
 def test_batch_equals_single_runs(lbm, dtype, scheme):
     print(f"case: batch {scheme} {dtype}", flush=True)
     b = make_batch(lbm, dtype, scheme=scheme, use_graph=False)
@@ -37,9 +51,30 @@ def test_batch_equals_single_runs(lbm, dtype, scheme):
         assert torch.equal(b.populations(j).cpu(), s.populations().cpu()), j
 
 
-def test_graph_replay_equals_eager(lbm):
-    a = make_batch(lbm, "f32", use_graph=False)
-    g = make_batch(lbm, "f32", use_graph=True, graph_steps=4)
+@pytest.mark.parametrize("block,cpt,waves,xcd", [(64, 1, -1, 1), (256, 2, 0, 0), (128, 4, 3, 1), (1024, 1, 6, 0),
+                                                 (512, 4, -1, 1)])
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_launch_shapes_equal_single_runs(lbm, scheme, block, cpt, waves, xcd):
+    """Every launch shape the autotuner may choose (block size, runs of cells
+    per block, residency cap, tiles dealt to the XCDs in parts or in order)
+    gives the single runs' bits."""
+    print(f"case: batch shape {scheme} block {block} cpt {cpt} waves {waves} xcd {xcd}", flush=True)
+    b = make_batch(lbm, "f32", scheme=scheme, use_graph=False, block_size=block, cells_per_thread=cpt,
+                   waves_per_simd=waves, xcd_split=xcd)
+    shape = b.launch_shape()
+    assert shape[:4] == (block, cpt, waves, xcd)
+    assert shape[4] == sum(edge_cells(n) for n, _, _ in MEMBERS)
+    b.step(9)
+    for j, (n, w, u) in enumerate(MEMBERS):
+        s = lbm.Lattice(19, n, scheme=scheme, collision="trt", omega=w, u_lid=u, dtype="f32")
+        s.step(9)
+        assert torch.equal(b.populations(j).cpu(), s.populations().cpu()), j
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_graph_replay_equals_eager(lbm, scheme):
+    a = make_batch(lbm, "f32", scheme=scheme, use_graph=False)
+    g = make_batch(lbm, "f32", scheme=scheme, use_graph=True, graph_steps=4)
     for n in (12, 3, 9):   # graph replays, odd remainders and a phase change
         a.step(n)
         g.step(n)
@@ -49,17 +84,19 @@ def test_graph_replay_equals_eager(lbm):
             assert torch.equal(a.populations(j).cpu(), g.populations(j).cpu()), (n, j)
 
 
-def test_sequential_equals_batched(lbm):
-    a = make_batch(lbm, "f32", use_graph=False)
-    s = make_batch(lbm, "f32", use_graph=False)
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_sequential_equals_batched(lbm, scheme):
+    a = make_batch(lbm, "f32", scheme=scheme, use_graph=False)
+    s = make_batch(lbm, "f32", scheme=scheme, use_graph=False)
     a.step(7)
     s.step_sequential(7)
     for j in range(len(MEMBERS)):
         assert torch.equal(a.populations(j).cpu(), s.populations(j).cpu()), j
 
 
-def test_fp64_batch_matches_oracle(lbm):
-    b = make_batch(lbm, "f64")
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_fp64_batch_matches_oracle(lbm, scheme):
+    b = make_batch(lbm, "f64", scheme=scheme)
     b.step(20)
     masses, kes = b.invariants()
     for j, (n, w, u) in enumerate(MEMBERS):
@@ -82,6 +119,8 @@ def test_autotuned_batch_is_still_correct(lbm):
     assert cells == sum(n ** 3 for n, _, _ in MEMBERS)
     assert fluid == sum((n - 2) ** 3 for n, _, _ in MEMBERS)
     assert blk in (64, 128, 256, 512, 1024)
+    shape = b.launch_shape()
+    assert shape[0] == blk and shape[1] in (1, 2, 4) and shape[2] in (-1, 0, 2, 3, 4, 6) and shape[3] in (0, 1)
     b.step(6)
     n, w, u = MEMBERS[1]
     ref = O.Simulation(O.Config(q=19, nx=n, ny=n, nz=n, model=O.TRT, omega=w, u_lid=(u, 0, 0)), "ref")
@@ -90,19 +129,20 @@ def test_autotuned_batch_is_still_correct(lbm):
 
 
 def test_autotune_cache_round_trip(lbm, tmp_path):
-    """The first autotuned creation appends its block size under the
-    ensemble's key; the second finds it and uses it without trial runs."""
+    """The first autotuned creation appends its launch shape (block size,
+    cells per thread, residency cap, XCD split) under the ensemble's key; the second
+    finds it and uses it without trial runs."""
     path = tmp_path / "tune.txt"
     cav = [lbm.Cavity(n, w, u) for n, w, u in MEMBERS]
     a = lbm.Batch(cav, scheme="aa", collision="trt", dtype="f32", autotune=True, autotune_cache=path)
-    blk = a.info()[2]
+    shape = a.launch_shape()[:4]
     a.close()
     lines = path.read_text().split("\n")
     assert len([l for l in lines if l.strip()]) == 1
-    key, value = lines[0].split()
-    assert int(value) == blk and key.startswith("gfx")
+    key, *values = lines[0].split()
+    assert tuple(int(v) for v in values) == shape and key.startswith("gfx")
     b = lbm.Batch(cav, scheme="aa", collision="trt", dtype="f32", autotune=True, autotune_cache=path)
-    assert b.info()[2] == blk
+    assert b.launch_shape()[:4] == shape
     b.step(4)
     b.close()
     assert len([l for l in path.read_text().split("\n") if l.strip()]) == 1
