@@ -367,8 +367,8 @@ def traffic_run(cav):
     torch.cuda.synchronize()
     del a, b
     torch.cuda.empty_cache()
-    for scheme, dtype in (("aa", "f64"), ("aa", "f32"), ("2pop", "f64"), ("swap", "f64"), ("2pop_pull", "f64"),
-                          ("2pop_pull", "f32")):
+    for scheme, dtype in (("aa", "f64"), ("aa", "f32"), ("aa", "f16"), ("2pop", "f64"), ("swap", "f64"),
+                          ("2pop_pull", "f64"), ("2pop_pull", "f32"), ("2pop_pull", "f16")):
         sim = lbm.Lattice(19, cav.n, scheme=scheme, collision="bgk", omega=cav.omega, u_lid=cav.u_lid, dtype=dtype)
         sim.step(4)
         sim.sync()
@@ -377,6 +377,23 @@ def traffic_run(cav):
                           "algorithmic_bytes_per_update": info.bytes_per_update, "copy_bytes": 2 * nbytes}),
               flush=True)
         sim.close()
+    # The 512-cavity ensemble (FP32-shifted TRT) at fixed launch shapes, 4 steps each.
+    from paper_2010_11751_amd import workloads as W
+    members = W.ensemble(512)
+    ens = [lbm.Cavity(m.n, m.omega, m.u_lid) for m in members]
+    stream = torch.cuda.Stream()
+    for scheme, shape in (("aa", (1024, 1, 4, 0)), ("2pop_pull", (512, 1, 0, 0))):
+        with torch.cuda.stream(stream):
+            b = lbm.Batch(ens, scheme=scheme, collision="trt", dtype="f32", use_graph=False, block_size=shape[0],
+                          cells_per_thread=shape[1], waves_per_simd=shape[2], xcd_split=shape[3])
+        b.step(4)
+        b.sync()
+        cells, fluid, _ = b.info()
+        print(json.dumps({"traffic_run": f"ensemble/{scheme}/f32", "fluid_cells": fluid, "cells": cells,
+                          "launch_shape": list(b.launch_shape()), "algorithmic_bytes_per_update": 153}), flush=True)
+        b.close()
+        del b
+        torch.cuda.empty_cache()
 
 
 def cpu_baseline(cav, budget_s: float = 12.0, max_steps: int = 20, single_budget_s: float = 8.0):
@@ -430,8 +447,9 @@ def main():
                     help="only the 512-cavity ensemble (AA and 2Pop pull; --steps graph steps, --warmup warm-up steps)")
     ap.add_argument("--traffic", action="store_true",
                     help="short run for hardware byte counters: one 1 GiB device copy, then 4 BGK steps of "
-                         "the 256^3 cavity each for AA FP64 / FP32-shifted, 2Pop FP64, swap FP64 and 2Pop pull "
-                         "FP64 / FP32-shifted")
+                         "the 256^3 cavity each for AA FP64 / FP32- / FP16-shifted, 2Pop FP64, swap FP64 and 2Pop "
+                         "pull FP64 / FP32- / FP16-shifted, then 4 steps each of the 512-cavity ensemble (AA and "
+                         "2Pop pull, FP32-shifted TRT)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the cavity step runs on a single MI355X; "
