@@ -126,6 +126,50 @@ def stream_copy_ceiling(cav, reps: int = 20):
     return out
 
 
+def pattern_probe(cav, reps: int = 20):
+    """The library's memory-pattern probe on the 256^3 cavity's cell count: 19
+    FP64 streams in the SoA layout of the step kernels (stride as the handle
+    pads it for this size) or in blocks of 2^8 / 2^12 cells holding all 19
+    streams, under the local, pull and AA-odd patterns, one or two values per
+    lane, uncapped and at 4 / 3 / 2 resident waves per SIMD. GB/s of moved
+    bytes (2 x 19 x 8 B per cell); the step kernels' algorithmic rates are
+    over the same bytes plus one flag byte per cell."""
+    import torch
+    from paper_2010_11751_amd import lbm
+    n = cav.cells
+    stride = (n + 1023) // 1024 * 1024
+    shift = (cav.n, cav.n)
+    size = 19 * stride + 2 * lbm.pattern_halo(12, shift)
+    a = torch.zeros(size, dtype=torch.float64, device="cuda")
+    b = torch.zeros_like(a)
+    caps = {"uncapped": 0, "4_waves": 35840, "3_waves": 46080, "2_waves": 65536}
+    rows = []
+    for layout in (0, 8, 12):
+        for pattern in (0, 1, 2):
+            for vec in ((1, 2) if layout == 0 else (1,)):
+                for cap, lds in caps.items():
+                    def go():
+                        lbm.pattern_copy(b, a, n, stride, layout, pattern, vec, lds, shift)
+                    go()
+                    torch.cuda.synchronize()
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(reps):
+                        go()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / reps
+                    rows.append({"layout": "soa" if layout == 0 else f"blocks_of_{1 << layout}",
+                                 "pattern": ("local", "pull", "aa_odd")[pattern], "values_per_lane": vec,
+                                 "residency": cap, "ms": round(ms, 4),
+                                 "gbs": round(2 * 19 * n * 8 / (ms * 1e-3) / 1e9, 1)})
+                    print(f"# probe {rows[-1]}", file=sys.stderr, flush=True)
+    del a, b
+    torch.cuda.empty_cache()
+    return rows
+
+
 def run_case(scheme, coll, dtype, steps, warmup, cav, reps=1):
     """One handle; `reps` timed runs of `steps` steps each (the first after
     `warmup` untimed steps); the median run is reported."""
@@ -443,6 +487,9 @@ def main():
                     help="only the periodic 256^3 Taylor-Green workload (2Pop pull and AA; FP64 / FP32 / FP16)")
     ap.add_argument("--validation", action="store_true",
                     help="only the cavity self-convergence study (Re 100, M = 32 / 64 / 128)")
+    ap.add_argument("--pattern-probe", action="store_true",
+                    help="only the memory-pattern probe (19 FP64 streams, SoA and blocked layouts, local / pull / "
+                         "AA-odd patterns) beside the FP64 step kernels of the 256^3 cavity")
     ap.add_argument("--ensemble", action="store_true",
                     help="only the 512-cavity ensemble (AA and 2Pop pull; --steps graph steps, --warmup warm-up steps)")
     ap.add_argument("--traffic", action="store_true",
@@ -471,6 +518,12 @@ def main():
         return
     if args.validation:
         validation()
+        return
+    if args.pattern_probe:
+        rows = pattern_probe(cav)
+        kernels = {f"{sch}/f64": round(run_case(sch, "bgk", "f64", 200, 20, cav, reps=3)["algorithmic_gbs"], 1)
+                   for sch in ("2pop_pull", "aa", "2pop")}
+        print(json.dumps({"pattern_probe": rows, "step_kernels_algorithmic_gbs": kernels}), flush=True)
         return
     if args.ensemble:
         seq = max(2, min(100, args.steps // 10))

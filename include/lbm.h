@@ -279,6 +279,26 @@ int lbm_device_copy(void *dst, const void *src, size_t bytes, void *stream);
 int lbm_stream_copy(void *dst, const void *src, int nstreams, size_t n, size_t stride, int lds_bytes, int ny,
                     int nz, void *stream);
 
+/* Memory-pattern probe over 19 FP64 streams of n values (not part of the
+ * method: the access patterns of the step kernels without their arithmetic,
+ * the ceilings they are compared with). Layout: block_log2 = 0 puts stream s
+ * at element offset s * stride (SoA, stride >= n); block_log2 = 8 or 12 puts
+ * the 19 streams of each block of 2^b cells together, value (s, j) at
+ * ((j >> b) * 19 + s) * 2^b + (j & (2^b - 1)) (stride unused; n a multiple of
+ * 2^b). pattern 0 reads and writes cell i; 1 reads stream s at i - d_s and
+ * writes it at i (2Pop pull); 2 reads at i - d_s and writes at i + d_s (AA
+ * odd), d_s = (c_sx ny + c_sy) nz + c_sz the offset of D3Q19 velocity s
+ * (ny, nz >= 1 for patterns 1 and 2). vec = 1 or 2 consecutive values per
+ * lane (2: SoA only; n a multiple of vec). Blocks of 256 threads ask for
+ * lds_bytes (0..65536) of unused dynamic LDS to cap residency. Device
+ * pointers to value (0, 0); with shifts both buffers must extend h values
+ * before it and after the last value, h = ny*nz + nz + 1 (SoA) or
+ * ceil((ny*nz + nz + 1) / 2^b) * 19 * 2^b (blocked), and 8-byte aligned
+ * (16-byte for vec = 2 unshifted). Asynchronous on `stream` (hipStream_t,
+ * may be NULL). */
+int lbm_pattern_copy(void *dst, const void *src, size_t n, size_t stride, int block_log2, int pattern, int vec,
+                     int lds_bytes, int ny, int nz, void *stream);
+
 /* Wait for all work queued on the handle's stream. */
 int lbm_sync(lbm_handle *h);
 

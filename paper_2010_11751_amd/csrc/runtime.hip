@@ -294,6 +294,56 @@ __global__ void __launch_bounds__(256) k_copy_streams(double* __restrict__ dst, 
     }
 }
 
+// Memory-pattern probe over the D3Q19 streams, FP64: value (s, j) at
+// s * stride + j (SoA, LB = 0) or in blocks of 2^LB cells holding all 19
+// streams, ((j >> LB) * 19 + s) << LB | (j & (2^LB - 1)). PAT 0: read and
+// write cell i (the local kinds); 1: read i - d_s, write i (2Pop pull);
+// 2: read i - d_s, write i + d_s (AA odd). VEC consecutive cells per lane
+// (SoA). All loads of a lane are issued before its stores, as in the step
+// kernels; nothing else is done with the values.
+template <int LB>
+__device__ __forceinline__ int64_t probe_at(int64_t j, int s, uint64_t stride)
+{
+    if constexpr (LB == 0) return (int64_t)s * (int64_t)stride + j;
+    else return ((j >> LB) * 19 + s) * ((int64_t)1 << LB) + (j & ((1 << LB) - 1));
+}
+
+template <int LB, int PAT, int VEC>
+__global__ void __launch_bounds__(256) k_pattern_copy(double* __restrict__ dst, const double* __restrict__ src,
+                                                      uint64_t stride, uint32_t n, int ny, int nz)
+{
+    typedef double V __attribute__((ext_vector_type(VEC), aligned(8)));
+    const uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+    if (i + VEC > n) return;
+    V v[19];
+#pragma unroll
+    for (int s = 0; s < 19; ++s) {
+        const int64_t d = PAT ? ((int64_t)L<19>::cx(s) * ny + L<19>::cy(s)) * nz + L<19>::cz(s) : 0;
+        v[s] = *reinterpret_cast<const V*>(src + probe_at<LB>((int64_t)i - d, s, stride));
+    }
+#pragma unroll
+    for (int s = 0; s < 19; ++s)
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) {
+            double t = v[s][c];
+            asm volatile("" : "+v"(t));
+            v[s][c] = t;
+        }
+#pragma unroll
+    for (int s = 0; s < 19; ++s) {
+        const int64_t d = PAT == 2 ? ((int64_t)L<19>::cx(s) * ny + L<19>::cy(s)) * nz + L<19>::cz(s) : 0;
+        *reinterpret_cast<V*>(dst + probe_at<LB>((int64_t)i + d, s, stride)) = v[s];
+    }
+}
+
+template <int LB, int PAT>
+void launch_pattern(int vec, uint32_t grid, uint32_t lds, hipStream_t st, double* dst, const double* src,
+                    uint64_t stride, uint32_t n, int ny, int nz)
+{
+    if (vec == 2) k_pattern_copy<LB, PAT, 2><<<grid, 256, lds, st>>>(dst, src, stride, n, ny, nz);
+    else k_pattern_copy<LB, PAT, 1><<<grid, 256, lds, st>>>(dst, src, stride, n, ny, nz);
+}
+
 }  // namespace
 
 // --- scratch of the no-allocation invariants entry point -----------------------
@@ -1305,6 +1355,35 @@ int lbm_device_copy(void* dst, const void* src, size_t bytes, void* stream)
     const uint32_t grid = (uint32_t)std::min<uint64_t>(grid_for(n, 256), 1u << 23);
     k_copy16<<<grid, 256, 0, (hipStream_t)stream>>>((uint4*)dst, (const uint4*)src, n);
     HIP_TRY(hipGetLastError(), "copy launch");
+    return LBM_OK;
+}
+
+int lbm_pattern_copy(void* dst, const void* src, size_t n, size_t stride, int block_log2, int pattern, int vec,
+                     int lds_bytes, int ny, int nz, void* stream)
+{
+    const bool blocked = block_log2 != 0;
+    if (!dst || !src || n == 0 || n > 0xffffffffull || (block_log2 != 0 && block_log2 != 8 && block_log2 != 12) ||
+        pattern < 0 || pattern > 2 || (vec != 1 && vec != 2) || (blocked && vec != 1) ||
+        lds_bytes < 0 || lds_bytes > 65536 || (pattern > 0 && (ny < 1 || nz < 1)) || (int64_t)ny * nz > (1ll << 30) ||
+        (!blocked && stride < n) || (blocked && n % ((size_t)1 << block_log2)) || n % (size_t)vec)
+        return fail(LBM_EINVAL, "pattern copy: 1..2^32-1 values, layout SoA (stride >= n) or blocks of 2^8 / 2^12 "
+                                "cells (n a multiple), pattern 0..2 with ny, nz >= 1 when shifted, 1 or 2 values "
+                                "per lane (SoA), LDS 0..65536");
+    const uint32_t grid = grid_for((uint64_t)n / vec, 256);
+    hipStream_t st = (hipStream_t)stream;
+    double* d = (double*)dst;
+    const double* sp = (const double*)src;
+    const uint32_t nn = (uint32_t)n, lds = (uint32_t)lds_bytes;
+    auto go = [&](auto lbc) {
+        constexpr int LB = decltype(lbc)::value;
+        if (pattern == 0) launch_pattern<LB, 0>(vec, grid, lds, st, d, sp, stride, nn, ny, nz);
+        else if (pattern == 1) launch_pattern<LB, 1>(vec, grid, lds, st, d, sp, stride, nn, ny, nz);
+        else launch_pattern<LB, 2>(vec, grid, lds, st, d, sp, stride, nn, ny, nz);
+    };
+    if (block_log2 == 0) go(std::integral_constant<int, 0>{});
+    else if (block_log2 == 8) go(std::integral_constant<int, 8>{});
+    else go(std::integral_constant<int, 12>{});
+    HIP_TRY(hipGetLastError(), "pattern copy launch");
     return LBM_OK;
 }
 

@@ -69,7 +69,7 @@ SYMBOLS = [
     "lbm_init_equilibrium", "lbm_set_geometry", "lbm_step", "lbm_macroscopic", "lbm_get_populations", "lbm_get_populations_at",
     "lbm_set_populations",
     "lbm_get_flags", "lbm_invariants", "lbm_invariants_noalloc", "lbm_neighbor_index", "lbm_get_info", "lbm_lattice", "lbm_device_copy",
-    "lbm_sync", "lbm_stream_copy",
+    "lbm_sync", "lbm_stream_copy", "lbm_pattern_copy",
     "lbm_last_error", "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_sequential",
     "lbm_batch_macroscopic", "lbm_batch_get_populations", "lbm_batch_invariants", "lbm_batch_info",
     "lbm_batch_launch_shape",
@@ -113,6 +113,7 @@ def lib() -> ctypes.CDLL:
     L.lbm_sync.argtypes = [P]
     L.lbm_device_copy.argtypes = [P, P, ctypes.c_size_t, P]
     L.lbm_stream_copy.argtypes = [P, P, I, ctypes.c_size_t, ctypes.c_size_t, I, I, I, P]
+    L.lbm_pattern_copy.argtypes = [P, P, ctypes.c_size_t, ctypes.c_size_t, I, I, I, I, I, I, P]
     L.lbm_last_error.argtypes = []
     L.lbm_last_error.restype = ctypes.c_char_p
     L.lbm_batch_create.argtypes = [I, ctypes.POINTER(CavityDesc), I, I, I, ctypes.POINTER(BatchOpts)]
@@ -168,6 +169,37 @@ def stream_copy(dst: torch.Tensor, src: torch.Tensor, nstreams: int, n: int, str
     check(lib().lbm_stream_copy(ctypes.c_void_p(dst.data_ptr() + off), ctypes.c_void_p(src.data_ptr() + off),
                                 nstreams, n, stride, lds_bytes, ny, nz,
                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+
+def pattern_halo(block_log2: int, shift) -> int:
+    """Values the pattern-copy buffers extend before value (0, 0) and after
+    the last value."""
+    if shift is None:
+        return 0
+    h = shift[0] * shift[1] + shift[1] + 1
+    if block_log2 == 0:
+        return h
+    b = 1 << block_log2
+    return -(-h // b) * 19 * b
+
+
+def pattern_copy(dst: torch.Tensor, src: torch.Tensor, n: int, stride: int, block_log2: int = 0, pattern: int = 0,
+                 vec: int = 1, lds_bytes: int = 0, shift=None) -> None:
+    """The library's memory-pattern probe over 19 FP64 streams on the current
+    stream: SoA (block_log2 0, stream s at s * stride) or blocks of 2^8 / 2^12
+    cells; pattern 0 local, 1 pull (read i - d_s), 2 AA odd (read i - d_s,
+    write i + d_s) with d_s from shift = (ny, nz). The tensors hold the halo
+    of pattern_halo() before value (0, 0) and after the last value."""
+    halo = pattern_halo(block_log2, shift if pattern else None)
+    span = 19 * (n if block_log2 else stride)
+    for t in (dst, src):
+        if t.dtype != torch.float64 or t.numel() < span + 2 * halo:
+            raise ValueError("float64 tensors of the layout's size plus twice the halo needed")
+    ny, nz = (0, 0) if not pattern else shift
+    off = halo * 8
+    check(lib().lbm_pattern_copy(ctypes.c_void_p(dst.data_ptr() + off), ctypes.c_void_p(src.data_ptr() + off), n,
+                                 stride, block_log2, pattern, vec, lds_bytes, ny, nz,
+                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
 
 
 def device_copy(dst: torch.Tensor, src: torch.Tensor) -> None:

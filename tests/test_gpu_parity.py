@@ -410,3 +410,42 @@ def test_stream_copy_probe(lbm, ns):
     for k in range(ns):
         off = (int(c[k, 0]) * ny + int(c[k, 1])) * nz + int(c[k, 2])
         assert np.array_equal(d_[halo + k * stride + i + off], s_[halo + k * stride + i - off]), k
+
+
+@pytest.mark.parametrize("block_log2", (0, 8, 12))
+@pytest.mark.parametrize("pattern", (0, 1, 2))
+@pytest.mark.parametrize("vec", (1, 2))
+def test_pattern_copy_probe(lbm, block_log2, pattern, vec):
+    """The memory-pattern probe moves each of the 19 streams as documented:
+    value (s, j) at s * stride + j (SoA) or ((j >> b) * 19 + s) * 2^b + (j mod
+    2^b) (blocked); read at i (- d_s for patterns 1 and 2), written at i
+    (+ d_s for pattern 2)."""
+    if block_log2 and vec == 2:
+        pytest.skip("two values per lane: SoA only")
+    ny, nz = 6, 5
+    n = 8192 if block_log2 else 3000
+    stride = 3072
+    shift = (ny, nz)
+    halo = lbm.pattern_halo(block_log2, shift if pattern else None)
+    span = 19 * (n if block_log2 else stride)
+    src = torch.randn(span + 2 * halo, dtype=torch.float64, device="cuda")
+    dst = torch.zeros_like(src)
+    lbm.pattern_copy(dst, src, n, stride, block_log2, pattern, vec, 0, shift)
+    torch.cuda.synchronize()
+    s_, d_ = src.cpu().numpy(), dst.cpu().numpy()
+    c, _, _ = O.lattice(19)
+
+    def at(j, k):
+        if block_log2 == 0:
+            return halo + k * stride + j
+        b = 1 << block_log2
+        return halo + ((j // b) * 19 + k) * b + j % b
+    i = np.arange(n)
+    written = np.zeros(d_.size, bool)
+    for k in range(19):
+        d = (int(c[k, 0]) * ny + int(c[k, 1])) * nz + int(c[k, 2])
+        r = i - d if pattern else i
+        w = i + d if pattern == 2 else i
+        assert np.array_equal(d_[at(w, k)], s_[at(r, k)]), k
+        written[at(w, k)] = True
+    assert float(np.abs(d_[~written]).max(initial=0.0)) == 0.0   # nothing else is written
