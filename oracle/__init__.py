@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.c")
 LIB = os.path.join(HERE, "liblbm_oracle.so")
 
-FLUID, WALL, LID = 0, 1, 2
+FLUID, WALL, LID, PRESSURE = 0, 1, 2, 3
 CAVITY, PERIODIC, CHANNEL = 0, 1, 2
 BGK, TRT, REG, RR = 0, 1, 2, 3
 NW4, RM, HM, CM, CHM, K = 4, 5, 6, 7, 8, 9
@@ -106,6 +106,9 @@ def lib():
         L.oracle_init_state.argtypes = [cfgp, P, P, P, P]
         L.oracle_init_state_ex.argtypes = [cfgp, P, P, P, P, P, P]
         L.oracle_reference_step.argtypes = [cfgp, P, P, P]
+        L.oracle_reference_step_ex.argtypes = [cfgp, P, P, P, P]
+        L.oracle_pull_step_ex.argtypes = [cfgp, P, P, P, P, P]
+        L.oracle_aa_natural_ex.argtypes = [cfgp, P, P, P, P]
         L.oracle_reference_cells.argtypes = [cfgp, P, P, P, ctypes.c_int64, P]
         L.oracle_2pop_step.argtypes = [cfgp, P, P, P, P]
         L.oracle_pull_step.argtypes = [cfgp, P, P, P, P]
@@ -179,9 +182,20 @@ def init_state(cfg: Config, fl: np.ndarray, rho=None, u=None, wall_u=None, wall_
     return pop
 
 
-def reference_step(cfg: Config, fl, f) -> np.ndarray:
+def _q(qlink, cfg):
+    if qlink is None:
+        return None
+    q = np.ascontiguousarray(qlink, dtype=np.float64).ravel()
+    if q.size != cfg.q * cfg.ntot or not np.all((q > 0.0) & (q <= 1.0)):
+        raise ValueError("qlink: q[k][Ntot] wall distances in (0, 1]")
+    return q
+
+
+def reference_step(cfg: Config, fl, f, qlink=None) -> np.ndarray:
+    """One reference step; qlink[k][Ntot] (optional) gives each fluid cell's
+    wall distance along -c_k for the curved-wall rule (1/2: half-way)."""
     new = np.empty_like(f)
-    _check(lib().oracle_reference_step(ctypes.byref(cfg.c_struct()), _p(fl), _p(f), _p(new)))
+    _check(lib().oracle_reference_step_ex(ctypes.byref(cfg.c_struct()), _p(fl), _p(f), _p(_q(qlink, cfg)), _p(new)))
     return new
 
 
@@ -198,8 +212,9 @@ def twopop_step(cfg: Config, fl, pop, out, order=None) -> None:
     _check(lib().oracle_2pop_step(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), _p(out), _p(order)))
 
 
-def pull_step(cfg: Config, fl, pop, out, order=None) -> None:
-    _check(lib().oracle_pull_step(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), _p(out), _p(order)))
+def pull_step(cfg: Config, fl, pop, out, order=None, qlink=None) -> None:
+    _check(lib().oracle_pull_step_ex(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), _p(_q(qlink, cfg)), _p(out),
+                                     _p(order)))
 
 
 def swap_step(cfg: Config, fl, pop, order=None) -> None:
@@ -210,9 +225,9 @@ def aa_step(cfg: Config, fl, pop, odd: bool, order=None) -> None:
     _check(lib().oracle_aa_step(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), int(bool(odd)), _p(order)))
 
 
-def aa_natural(cfg: Config, fl, pop) -> np.ndarray:
+def aa_natural(cfg: Config, fl, pop, qlink=None) -> np.ndarray:
     f = np.empty_like(pop)
-    _check(lib().oracle_aa_natural(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), _p(f)))
+    _check(lib().oracle_aa_natural_ex(ctypes.byref(cfg.c_struct()), _p(fl), _p(pop), _p(_q(qlink, cfg)), _p(f)))
     return f
 
 
@@ -245,11 +260,14 @@ class Simulation:
     pre-collision populations f[k][Ntot] at whole steps."""
 
     def __init__(self, cfg: Config, scheme: str = "2pop", rho=None, u=None, order=None, cell_types=None,
-                 wall_u=None, wall_rho=None):
-        """cell_types (uint8 FLUID / WALL / LID per cell) replaces the
-        geometry's flags; wall_u[3][Ntot] and wall_rho[Ntot] give each wall
-        cell its own velocity and density."""
-        self.cfg, self.scheme, self.order = cfg, scheme, order
+                 wall_u=None, wall_rho=None, qlink=None):
+        """cell_types (uint8 FLUID / WALL / LID / PRESSURE per cell) replaces
+        the geometry's flags; wall_u[3][Ntot] and wall_rho[Ntot] give each wall
+        cell its own velocity and density; qlink[k][Ntot] the curved-wall
+        distances (reference step and 2Pop pull only)."""
+        if qlink is not None and scheme not in ("ref", "2pop_pull"):
+            raise ValueError("curved walls: reference step and 2Pop pull only")
+        self.cfg, self.scheme, self.order, self.qlink = cfg, scheme, order, qlink
         self.flags = flags(cfg) if cell_types is None else np.ascontiguousarray(cell_types, dtype=np.uint8).copy()
         self.pop = init_state(cfg, self.flags, rho, u, wall_u, wall_rho)
         self.out = self.pop.copy() if scheme in ("2pop", "2pop_pull") else None
@@ -258,7 +276,7 @@ class Simulation:
     def step(self, n: int = 1) -> None:
         for _ in range(n):
             if self.scheme == "ref":
-                self.pop = reference_step(self.cfg, self.flags, self.pop)
+                self.pop = reference_step(self.cfg, self.flags, self.pop, self.qlink)
             elif self.scheme == "2pop":
                 twopop_step(self.cfg, self.flags, self.pop, self.out, self.order)
                 self.pop, self.out = self.out, self.pop
@@ -270,7 +288,7 @@ class Simulation:
                 if self.t == 0:
                     aa_step(self.cfg, self.flags, self.pop, False, self.order)
                 else:
-                    pull_step(self.cfg, self.flags, self.pop, self.out, self.order)
+                    pull_step(self.cfg, self.flags, self.pop, self.out, self.order, self.qlink)
                     self.pop, self.out = self.out, self.pop
             else:
                 raise ValueError(self.scheme)
@@ -279,7 +297,7 @@ class Simulation:
     def natural(self) -> np.ndarray:
         """Pre-collision populations in the configured layout."""
         if (self.scheme == "aa" and self.t % 2 == 1) or (self.scheme == "2pop_pull" and self.t > 0):
-            return aa_natural(self.cfg, self.flags, self.pop)
+            return aa_natural(self.cfg, self.flags, self.pop, self.qlink)
         return self.pop.copy()
 
     def populations(self) -> np.ndarray:

@@ -40,6 +40,14 @@
  *   invariants ................ pinned (mass and kinetic energy of states
  *                               built from given rho and u fields equal
  *                               sum rho and 1/2 sum rho |u|^2 of those fields)
+ *   curved walls .............. pinned (q = 1/2 is the half-way wall bit for
+ *                               bit; plane Couette flow between walls at any
+ *                               q is the exact straight line through the
+ *                               wall positions; pull scheme = reference step)
+ *   pressure walls ............ pinned (a fluid at rest at the walls' density
+ *                               is a fixed point; a pressure-driven channel
+ *                               takes the parabola of its density drop; the
+ *                               schemes agree bit for bit)
  */
 #include <math.h>
 #ifdef _OPENMP
@@ -52,7 +60,7 @@
 /* ------------------------------------------------------------------------- */
 /* Configuration, as passed from Python (ctypes Structure of the same shape). */
 
-enum { O_FLUID = 0, O_WALL = 1, O_LID = 2 };
+enum { O_FLUID = 0, O_WALL = 1, O_LID = 2, O_PRESSURE = 3 };
 enum { O_CAVITY = 0, O_PERIODIC = 1, O_CHANNEL = 2 };
 enum { O_BGK = 0, O_TRT = 1, O_REG = 2, O_RR = 3,
        O_NW4 = 4, O_RM = 5, O_HM = 6, O_CM = 7, O_CHM = 8, O_K = 9 };
@@ -218,6 +226,35 @@ static double wall_term(const olat *L, const ocfg *g, uint8_t flag, int k)
     double uw[3] = {0.0, 0.0, 0.0};
     if (flag == O_LID) { uw[0] = g->u_lid[0]; uw[1] = g->u_lid[1]; uw[2] = g->u_lid[2]; }
     return -6.0 * L->t[k] * (L->c[k][0] * uw[0] + L->c[k][1] * uw[1] + L->c[k][2] * uw[2]);
+}
+
+/* Boundary extensions of the link-wise bounce-back (Sec. 1.1 notes that it
+ * extends to curved walls while staying local; Eq. momentum-exchange has the
+ * wall density rho_w).
+ *
+ * Pressure (density) walls: a cell of type O_PRESSURE reflects a population
+ * with the opposite sign, f_kbar(x) = -f_out_k(x) + a_k, and stores
+ * a_k = 2 t_k rho_w [1 + 9/2 (c_k . u_w)^2 - 3/2 |u_w|^2] in its slot k:
+ * twice the even part of the equilibrium at (rho_w, u_w), so that the
+ * density, not the velocity, is set at the half-way wall (anti-bounce-back).
+ * Every bounce-back site reads the sign from the wall cell's type. */
+static double reflected(uint8_t wall, double v) { return wall == O_PRESSURE ? -v : v; }
+
+/* Curved walls: the wall crosses the link from fluid cell x to the wall cell
+ * s = x - c_k at the fraction q of the link from x (0 < q <= 1; q = 1/2 is
+ * the half-way wall). The population entering x in direction k is the linear
+ * interpolated bounce-back, written with post-collision values only:
+ *   q >= 1/2: [f_out_kbar(x) + (2q - 1) f_out_k(x) + w_kbar(s)] / (2q)
+ *   q <  1/2: 2q f_out_kbar(x) + (1 - 2q) f_out_kbar(x + c_k) + w_kbar(s)
+ * f_out_kbar(x + c_k) is the value that streams into x along the same line
+ * from the other side (f_out_kbar(x) when x + c_k is not fluid). Both forms
+ * give the half-way rule at q = 1/2, and both read only values that a cell
+ * gathering its populations (the pull form) reads for itself. */
+static double curved_link(double q, double fo_kbar_x, double fo_k_x, double fo_kbar_n, double w)
+{
+    if (q == 0.5) return fo_kbar_x + w;
+    if (q > 0.5) return (fo_kbar_x + (2.0 * q - 1.0) * fo_k_x + w) / (2.0 * q);
+    return 2.0 * q * fo_kbar_x + (1.0 - 2.0 * q) * fo_kbar_n + w;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -650,7 +687,8 @@ int oracle_collide(const ocfg *g, const double *f, double *fout)
 
 /* ------------------------------------------------------------------------- */
 /* State set-up: wall cells hold their momentum-exchange terms in every slot
- * (Eq. storage2), fluid cells hold E(rho, u) (Eq. storage1). rho and u may be
+ * (Eq. storage2; pressure cells their anti-bounce-back terms), fluid cells
+ * hold E(rho, u) (Eq. storage1). rho and u may be
  * NULL (rho = 1, u = 0); u is given as u[3][Ntot]. The equilibrium is the
  * model's own (E^S for RR, the NW4 equilibrium for the moment-space models). */
 int oracle_init_state_ex(const ocfg *g, const uint8_t *flags, const double *rho, const double *u,
@@ -665,7 +703,13 @@ int oracle_init_state_ex(const ocfg *g, const uint8_t *flags, const double *rho,
             /* Eq. storage2 with the cell's own wall velocity and density when
              * given: -6 t_k rho_w c_k . u_w. */
             for (k = 0; k < L.q; ++k) {
-                if (wall_u || wall_rho) {
+                if (flags[i] == O_PRESSURE) {
+                    double uw[3] = {0.0, 0.0, 0.0}, rw = wall_rho ? wall_rho[i] : 1.0, cu, uu;
+                    if (wall_u) { uw[0] = wall_u[i]; uw[1] = wall_u[n + i]; uw[2] = wall_u[2 * n + i]; }
+                    cu = L.c[k][0] * uw[0] + L.c[k][1] * uw[1] + L.c[k][2] * uw[2];
+                    uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+                    pop[at(g, i, k)] = 2.0 * L.t[k] * rw * (1.0 + 4.5 * cu * cu - 1.5 * uu);
+                } else if (wall_u || wall_rho) {
                     double uw[3] = {0.0, 0.0, 0.0}, rw = wall_rho ? wall_rho[i] : 1.0;
                     if (wall_u) { uw[0] = wall_u[i]; uw[1] = wall_u[n + i]; uw[2] = wall_u[2 * n + i]; }
                     pop[at(g, i, k)] = -6.0 * L.t[k] * rw *
@@ -698,10 +742,13 @@ int oracle_init_state(const ocfg *g, const uint8_t *flags, const double *rho,
  * its upstream neighbour s = x - c_k; if s is not fluid the link is bounced
  * back at the half-way wall, f_k(x) = f_out_kbar(x) + w_kbar(s)
  * (Eq. momentum-exchange with k and k-bar exchanged), w_kbar(s) being the
- * term the wall cell s stores in its slot k-bar (Eq. storage2). The rest
- * population stays. Wall cells keep their stored terms. fnew must not alias
- * f. */
-int oracle_reference_step(const ocfg *g, const uint8_t *flags, const double *f, double *fnew)
+ * term the wall cell s stores in its slot k-bar (Eq. storage2); a pressure
+ * cell reflects with the opposite sign, and a link with a wall distance
+ * qlink[k][x] other than 1/2 takes the curved-wall rule (qlink may be NULL:
+ * every wall half-way). The rest population stays. Wall cells keep their
+ * stored terms. fnew must not alias f. */
+int oracle_reference_step_ex(const ocfg *g, const uint8_t *flags, const double *f, const double *qlink,
+                             double *fnew)
 {
     olat L;
     int64_t i, n = ntot(g);
@@ -731,12 +778,25 @@ int oracle_reference_step(const ocfg *g, const uint8_t *flags, const double *f, 
             int64_t s;
             if (k == L.rest) { fnew[at(g, i, k)] = fo[at(g, i, k)]; continue; }
             s = neighbour(g, i, L.c[k], -1);
-            if (flags[s] == O_FLUID) fnew[at(g, i, k)] = fo[at(g, s, k)];
-            else fnew[at(g, i, k)] = fo[at(g, i, L.opp[k])] + f[at(g, s, L.opp[k])];
+            if (flags[s] == O_FLUID) {
+                fnew[at(g, i, k)] = fo[at(g, s, k)];
+            } else if (flags[s] == O_PRESSURE || !qlink) {
+                fnew[at(g, i, k)] = reflected(flags[s], fo[at(g, i, L.opp[k])]) + f[at(g, s, L.opp[k])];
+            } else {
+                int64_t nb = neighbour(g, i, L.c[k], +1);
+                double fo_n = flags[nb] == O_FLUID ? fo[at(g, nb, L.opp[k])] : fo[at(g, i, L.opp[k])];
+                fnew[at(g, i, k)] = curved_link(qlink[(int64_t)k * n + i], fo[at(g, i, L.opp[k])],
+                                                fo[at(g, i, k)], fo_n, f[at(g, s, L.opp[k])]);
+            }
         }
     }
     free(fo);
     return 0;
+}
+
+int oracle_reference_step(const ocfg *g, const uint8_t *flags, const double *f, double *fnew)
+{
+    return oracle_reference_step_ex(g, flags, f, NULL, fnew);
 }
 
 /* The reference step for a list of cells only: new populations of cell
@@ -767,7 +827,7 @@ int oracle_reference_cells(const ocfg *g, const uint8_t *flags, const double *f,
                 collide(&L, g, cell, out);
                 fnew[j * L.q + k] = out[k];
             } else {
-                fnew[j * L.q + k] = own[L.opp[k]] + f[at(g, s, L.opp[k])];
+                fnew[j * L.q + k] = reflected(flags[s], own[L.opp[k]]) + f[at(g, s, L.opp[k])];
             }
         }
     }
@@ -802,7 +862,7 @@ int oracle_2pop_step(const ocfg *g, const uint8_t *flags, const double *pop, dou
             if (k == L.rest) { out[at(g, i, k)] = fo[k]; continue; }
             nb = neighbour(g, i, L.c[k], +1);
             if (flags[nb] == O_FLUID) out[at(g, nb, k)] = fo[k];              /* nb_out_k <- pop_k        */
-            else out[at(g, i, L.opp[k])] = fo[k] + pop[at(g, nb, k)];        /* out_kbar <- pop_k + nb_pop_k */
+            else out[at(g, i, L.opp[k])] = reflected(flags[nb], fo[k]) + pop[at(g, nb, k)]; /* out_kbar <- pop_k + nb_pop_k */
         }
     }
     return 0;
@@ -842,10 +902,10 @@ int oracle_swap_step(const ocfg *g, const uint8_t *flags, double *pop, const int
                     pop[at(g, i, L.opp[k])] = pop[at(g, nb, k)];
                     pop[at(g, nb, k)] = tmp;
                 } else {                                                     /* pop_kbar += nb_pop_k */
-                    pop[at(g, i, L.opp[k])] = pop[at(g, i, L.opp[k])] + pop[at(g, nb, k)];
+                    pop[at(g, i, L.opp[k])] = reflected(flags[nb], pop[at(g, i, L.opp[k])]) + pop[at(g, nb, k)];
                 }
             } else if (flags[nb] == O_FLUID) {                               /* wall: nb_pop_k += pop_kbar */
-                pop[at(g, nb, k)] = pop[at(g, nb, k)] + pop[at(g, i, L.opp[k])];
+                pop[at(g, nb, k)] = reflected(flags[i], pop[at(g, nb, k)]) + pop[at(g, i, L.opp[k])];
             }
         }
     }
@@ -879,7 +939,7 @@ int oracle_aa_step(const ocfg *g, const uint8_t *flags, double *pop, int odd, co
             if (k == L.rest) { tmp[k] = pop[at(g, i, k)]; continue; }
             s = neighbour(g, i, L.c[k], -1);
             if (flags[s] == O_FLUID) tmp[k] = pop[at(g, s, L.opp[k])];
-            else tmp[k] = pop[at(g, i, k)] + pop[at(g, s, L.opp[k])];
+            else tmp[k] = reflected(flags[s], pop[at(g, i, k)]) + pop[at(g, s, L.opp[k])];
         }
         collide(&L, g, tmp, fo);
         for (k = 0; k < L.q; ++k) {
@@ -887,7 +947,7 @@ int oracle_aa_step(const ocfg *g, const uint8_t *flags, double *pop, int odd, co
             if (k == L.rest) { pop[at(g, i, k)] = fo[k]; continue; }
             nb = neighbour(g, i, L.c[k], +1);
             if (flags[nb] == O_FLUID) pop[at(g, nb, k)] = fo[k];
-            else pop[at(g, i, L.opp[k])] = fo[k] + pop[at(g, nb, k)];
+            else pop[at(g, i, L.opp[k])] = reflected(flags[nb], fo[k]) + pop[at(g, nb, k)];
         }
     }
     return 0;
@@ -900,8 +960,8 @@ int oracle_aa_step(const ocfg *g, const uint8_t *flags, double *pop, int odd, co
  * or pop_k(x) + pop_kbar(x - c_k) across a wall, collides, and stores f_out_k
  * at out_kbar(x); the caller then exchanges the arrays. Both arrays hold the
  * wall terms in wall cells. */
-int oracle_pull_step(const ocfg *g, const uint8_t *flags, const double *pop, double *out,
-                     const int64_t *order)
+int oracle_pull_step_ex(const ocfg *g, const uint8_t *flags, const double *pop, const double *qlink, double *out,
+                        const int64_t *order)
 {
     olat L;
     int64_t j, n = ntot(g);
@@ -916,8 +976,15 @@ int oracle_pull_step(const ocfg *g, const uint8_t *flags, const double *pop, dou
             int64_t s;
             if (k == L.rest) { tmp[k] = pop[at(g, i, k)]; continue; }
             s = neighbour(g, i, L.c[k], -1);
-            if (flags[s] == O_FLUID) tmp[k] = pop[at(g, s, L.opp[k])];
-            else tmp[k] = pop[at(g, i, k)] + pop[at(g, s, L.opp[k])];
+            if (flags[s] == O_FLUID) {
+                tmp[k] = pop[at(g, s, L.opp[k])];
+            } else if (flags[s] == O_PRESSURE || !qlink) {
+                tmp[k] = reflected(flags[s], pop[at(g, i, k)]) + pop[at(g, s, L.opp[k])];
+            } else {  /* slot k of a cell holds f_out_kbar: see curved_link */
+                int64_t nb = neighbour(g, i, L.c[k], +1);
+                tmp[k] = curved_link(qlink[(int64_t)k * n + i], pop[at(g, i, k)], pop[at(g, i, L.opp[k])],
+                                     pop[at(g, flags[nb] == O_FLUID ? nb : i, k)], pop[at(g, s, L.opp[k])]);
+            }
         }
         collide(&L, g, tmp, fo);
         for (k = 0; k < L.q; ++k) out[at(g, i, L.opp[k])] = fo[k];
@@ -925,9 +992,15 @@ int oracle_pull_step(const ocfg *g, const uint8_t *flags, const double *pop, dou
     return 0;
 }
 
+int oracle_pull_step(const ocfg *g, const uint8_t *flags, const double *pop, double *out,
+                     const int64_t *order)
+{
+    return oracle_pull_step_ex(g, flags, pop, NULL, out, order);
+}
+
 /* Natural pre-collision populations of an AA array left by an even step:
  * the odd-step pull without the collision. Wall cells copy their terms. */
-int oracle_aa_natural(const ocfg *g, const uint8_t *flags, const double *pop, double *f)
+int oracle_aa_natural_ex(const ocfg *g, const uint8_t *flags, const double *pop, const double *qlink, double *f)
 {
     olat L;
     int64_t i, n = ntot(g);
@@ -938,11 +1011,23 @@ int oracle_aa_natural(const ocfg *g, const uint8_t *flags, const double *pop, do
             int64_t s;
             if (flags[i] != O_FLUID || k == L.rest) { f[at(g, i, k)] = pop[at(g, i, k)]; continue; }
             s = neighbour(g, i, L.c[k], -1);
-            if (flags[s] == O_FLUID) f[at(g, i, k)] = pop[at(g, s, L.opp[k])];
-            else f[at(g, i, k)] = pop[at(g, i, k)] + pop[at(g, s, L.opp[k])];
+            if (flags[s] == O_FLUID) {
+                f[at(g, i, k)] = pop[at(g, s, L.opp[k])];
+            } else if (flags[s] == O_PRESSURE || !qlink) {
+                f[at(g, i, k)] = reflected(flags[s], pop[at(g, i, k)]) + pop[at(g, s, L.opp[k])];
+            } else {
+                int64_t nb = neighbour(g, i, L.c[k], +1);
+                f[at(g, i, k)] = curved_link(qlink[(int64_t)k * n + i], pop[at(g, i, k)], pop[at(g, i, L.opp[k])],
+                                             pop[at(g, flags[nb] == O_FLUID ? nb : i, k)], pop[at(g, s, L.opp[k])]);
+            }
         }
     }
     return 0;
+}
+
+int oracle_aa_natural(const ocfg *g, const uint8_t *flags, const double *pop, double *f)
+{
+    return oracle_aa_natural_ex(g, flags, pop, NULL, f);
 }
 
 /* ------------------------------------------------------------------------- */
