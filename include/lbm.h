@@ -105,7 +105,7 @@ enum lbm_collision {
 enum lbm_dtype { LBM_F64 = 0, LBM_F32_SHIFTED = 1, LBM_F16_SHIFTED = 2 };
 enum lbm_layout { LBM_SOA = 0, LBM_AOS = 1 };
 enum lbm_geometry { LBM_CAVITY = 0, LBM_PERIODIC = 1, LBM_CHANNEL = 2 };
-enum lbm_flag { LBM_FLUID = 0, LBM_WALL = 1, LBM_LID = 2 };
+enum lbm_flag { LBM_FLUID = 0, LBM_WALL = 1, LBM_LID = 2, LBM_PRESSURE = 3 };
 enum lbm_ptr_kind { LBM_PTR_DEVICE = 0, LBM_PTR_HOST = 1 };
 
 typedef struct lbm_handle lbm_handle;
@@ -189,10 +189,14 @@ int lbm_init_equilibrium(lbm_handle *h, const double *rho, const double *u);
 /* Replace the geometry by caller cell types (Sec. 2.1: link-wise bounce-back
  * Dirichlet walls with the momentum-exchange term of Eq. momentum-exchange,
  * stored in the wall cells as Eq. storage2). type[Ntot] holds LBM_FLUID,
- * LBM_WALL or LBM_LID per cell (LID is a wall like any other here). Each wall
- * cell stores -6 t_k rho_w c_k . u_w from its own wall velocity
- * wall_velocity[3][Ntot] (SoA; NULL: at rest) and wall density
- * wall_density[Ntot] (NULL: 1); values of fluid cells are ignored. The box
+ * LBM_WALL, LBM_LID or LBM_PRESSURE per cell (LID is a wall like any other
+ * here). Each wall cell stores -6 t_k rho_w c_k . u_w from its own wall
+ * velocity wall_velocity[3][Ntot] (SoA; NULL: at rest) and wall density
+ * wall_density[Ntot] (NULL: 1); values of fluid cells are ignored.
+ * LBM_PRESSURE cells are density (pressure) walls: a population reaching one
+ * comes back with the opposite sign plus the stored term
+ * 2 t_k rho_w [1 + 9/2 (c_k . u_w)^2 - 3/2 |u_w|^2] (anti-bounce-back, the
+ * wall density set half-way along the link), in every scheme. The box
  * faces of axes that do not wrap (all of them for LBM_CAVITY, z for
  * LBM_CHANNEL) must be walls; |u_w| < 0.4 and 0 < rho_w < 10. Otherwise
  * returns LBM_EINVAL and leaves the handle unchanged. On success the fluid
@@ -201,6 +205,22 @@ int lbm_init_equilibrium(lbm_handle *h, const double *rho, const double *u);
  * ptr_kind; the caller keeps ownership. */
 int lbm_set_geometry(lbm_handle *h, const uint8_t *type, const double *wall_velocity,
                      const double *wall_density);
+
+/* Curved walls (Sec. 1.1: the link-wise bounce-back extends to curved walls
+ * while staying local). q[k][Ntot] (FP64, follows ptr_kind) gives, for every
+ * fluid cell x and direction k whose upstream cell x - c_k is a wall (not a
+ * pressure wall), the fraction 0 < q <= 1 of the link from x at which the
+ * wall lies; other entries are ignored but must lie in (0, 1] too. The
+ * population entering x is then the linear interpolated bounce-back
+ *   q >= 1/2: [f_out_kbar(x) + (2q - 1) f_out_k(x) + w_kbar] / (2q)
+ *   q <  1/2: 2q f_out_kbar(x) + (1 - 2q) f_out_kbar(x + c_k) + w_kbar
+ * (f_out_kbar(x) in place of f_out_kbar(x + c_k) when x + c_k is not fluid),
+ * the half-way rule at q = 1/2. All of these are values a cell gathering its
+ * own populations reads, so the rule needs the 2Pop pull scheme: other
+ * schemes return LBM_EUNSUPPORTED unless every q is 1/2 (which restores the
+ * plain rule). Out-of-range values: LBM_EINVAL, handle unchanged. The
+ * populations are kept; the rule applies from the next step. */
+int lbm_set_wall_distances(lbm_handle *h, const double *q);
 
 /* Advance n >= 0 time steps (asynchronous on the handle's stream unless the
  * invariant monitor is on). AA phase is tracked, so any n is allowed.

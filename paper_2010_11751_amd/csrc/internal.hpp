@@ -14,6 +14,7 @@ enum : uint8_t {
     FL_FLUID = 0,
     FL_WALL = 1,
     FL_LID = 2,
+    FL_PRESSURE = 3,  // pressure (density) wall: anti-bounce-back
     // Bits 2-4: wall plane of a fluid cell whose non-fluid neighbours are
     // exactly the nine on one side (1 x-1, 2 x+1, 3 y-1, 4 y+1, 5 z-1,
     // 6 z+1); such cells stay on the fast path.
@@ -87,6 +88,8 @@ struct Field {
     int nx, ny, nz;
     int reverse;           // visit cells in reverse block / list order (traversal-order tests)
     int custom_walls;      // wall terms set per cell by the caller (else: from type and lid)
+    const double* qlink;   // curved walls: q[k][ntot], the wall's fraction of the link from a
+                           //   fluid cell x to the wall cell x - c_k (null: all half-way)
     LidTerms lid;          // terms of lid cells (built-in geometries)
 };
 

@@ -133,6 +133,49 @@ __device__ __forceinline__ int32_t offset(const Field& F)
 
 __device__ __forceinline__ bool is_fluid(const Field& F, uint32_t j) { return (F.flags[j] & FL_TYPE) == FL_FLUID; }
 
+// A population bounced back at the non-fluid cell j: pressure walls reflect
+// it with the opposite sign (anti-bounce-back), the others as it is.
+template <class R>
+__device__ __forceinline__ R reflect(const Field& F, uint32_t j, R v)
+{
+    return (F.flags[j] & FL_TYPE) == FL_PRESSURE ? -v : v;
+}
+
+// Curved wall on the link from fluid cell x to the wall cell s = x - c_k at
+// the fraction q of the link from x (linear interpolated bounce-back in pull
+// form; q = 1/2 is the half-way wall): the population entering x in
+// direction k from the post-collision values f_out_kbar(x), f_out_k(x),
+// f_out_kbar(x + c_k) (the value streaming in along the same line from the
+// other side; f_out_kbar(x) when x + c_k is not fluid) and the wall term w.
+template <class R>
+__device__ __forceinline__ R curved_link(double q, R fo_kbar_x, R fo_k_x, R fo_kbar_n, R w)
+{
+    if (q == 0.5) return fo_kbar_x + w;
+    const R qq = R(q);
+    if (q > 0.5) return (fo_kbar_x + (R(2) * qq - R(1)) * fo_k_x + w) / (R(2) * qq);
+    return R(2) * qq * fo_kbar_x + (R(1) - R(2) * qq) * fo_kbar_n + w;
+}
+
+// Gathered population f_k(x) across the non-fluid cell s = x - c_k in pull
+// form, from an array holding f_out_kbar in slot k (AA after an even step,
+// 2Pop pull): slot k of x plus (or, at a pressure wall, minus) the wall's
+// slot kbar; on a curved link the interpolated rule.
+template <int Q, int K, class ST, class A>
+__device__ __forceinline__ real_t<ST> gather_across(const Field& F, const A& a, uint32_t i, uint32_t s, bool border,
+                                                    const Coord& c)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    const R w = a.ld(s, S::opp(K));
+    if (F.qlink && !((F.flags[s] & FL_TYPE) == FL_PRESSURE)) {
+        const uint32_t n = neighbour<Q, K, 1>(F, i, border, c);
+        const R own = a.ld(i, K);
+        return curved_link<R>(F.qlink[(size_t)K * F.ntot + i], own, a.ld(i, S::opp(K)),
+                              is_fluid(F, n) ? a.ld(n, K) : own, w);
+    }
+    return reflect(F, s, a.ld(i, K)) + w;
+}
+
 template <class R>
 __device__ __forceinline__ Relax<R> relax_of(const RelaxD& p)
 {
@@ -218,7 +261,7 @@ __device__ __forceinline__ void push_2pop_slow(const Field& F, uint32_t i, uint8
         } else {
             const uint32_t j = neighbour<Q, k, 1>(F, i, border, c);
             if (is_fluid(F, j)) dst.st(j, k, g[k]);
-            else dst.st(i, S::opp(k), g[k] + src.ld(j, k));
+            else dst.st(i, S::opp(k), reflect(F, j, g[k]) + src.ld(j, k));
         }
     });
 }
@@ -301,10 +344,10 @@ __device__ __forceinline__ void swap_stream_slow(const Field& F, uint32_t i, uin
             *a.ptr(i, S::opp(k)) = t;
             *a.ptr(j, k) = m;
         } else {
-            a.st(i, S::opp(k), a.ld(i, S::opp(k)) + a.ld(j, k));
+            a.st(i, S::opp(k), reflect(F, j, a.ld(i, S::opp(k))) + a.ld(j, k));
         }
         const uint32_t s = neighbour<Q, k, -1>(F, i, border, c);
-        if (!is_fluid(F, s)) a.st(i, k, a.ld(i, k) + a.ld(s, S::opp(k)));
+        if (!is_fluid(F, s)) a.st(i, k, reflect(F, s, a.ld(i, k)) + a.ld(s, S::opp(k)));
     });
 }
 
@@ -373,7 +416,7 @@ __device__ __forceinline__ void aa_odd_slow(const Field& F, const Relax<real_t<S
         } else {
             const uint32_t s = neighbour<Q, k, -1>(F, i, border, c);
             if (is_fluid(F, s)) g[k] = a.ld(s, S::opp(k));
-            else g[k] = a.ld(i, k) + a.ld(s, S::opp(k));
+            else g[k] = reflect(F, s, a.ld(i, k)) + a.ld(s, S::opp(k));
         }
     });
     collide<Q, MODEL, ST::shifted>(g, p);
@@ -384,7 +427,7 @@ __device__ __forceinline__ void aa_odd_slow(const Field& F, const Relax<real_t<S
         } else {
             const uint32_t j = neighbour<Q, k, 1>(F, i, border, c);
             if (is_fluid(F, j)) a.st(j, k, g[k]);
-            else a.st(i, S::opp(k), g[k] + a.ld(j, k));
+            else a.st(i, S::opp(k), reflect(F, j, g[k]) + a.ld(j, k));
         }
     });
 }
@@ -470,7 +513,7 @@ __device__ __forceinline__ void pull_slow(const Field& F, const Relax<real_t<ST>
         } else {
             const uint32_t s = neighbour<Q, k, -1>(F, i, border, c);
             if (is_fluid(F, s)) g[k] = a.ld(s, S::opp(k));
-            else g[k] = a.ld(i, k) + a.ld(s, S::opp(k));
+            else g[k] = gather_across<Q, k, ST>(F, a, i, s, border, c);
         }
     });
     collide<Q, MODEL, ST::shifted>(g, p);
@@ -913,7 +956,9 @@ __device__ __forceinline__ void natural_cell(const Field& F, uint32_t i, int aa_
     const Acc<ST, LAYOUT, Q> a{(typename ST::T*)F.pop, F.stride};
     const uint8_t fl = F.flags[i];
     if ((fl & FL_TYPE) != FL_FLUID) {
-        static_for<0, Q>([&](auto K) { f[K] = double(a.ld(i, K)); });
+        // a pressure wall's term is stored less 2 t_k in shifted storage
+        const bool p = ST::shifted && (fl & FL_TYPE) == FL_PRESSURE;
+        static_for<0, Q>([&](auto K) { f[K] = double(a.ld(i, K)) + (p ? 2.0 * S::t(K) : 0.0); });
         return;
     }
     const bool border = fl & FL_BORDER;
@@ -926,7 +971,7 @@ __device__ __forceinline__ void natural_cell(const Field& F, uint32_t i, int aa_
         } else {
             const uint32_t s = neighbour<Q, k, -1>(F, i, border, c);
             if (is_fluid(F, s)) v = a.ld(s, S::opp(k));
-            else v = a.ld(i, k) + a.ld(s, S::opp(k));
+            else v = gather_across<Q, k, ST>(F, a, i, s, border, c);
         }
         f[k] = ST::shifted ? double(v) + S::t(k) : double(v);
     });
@@ -1023,7 +1068,26 @@ __global__ void k_init(Field F, InitArgs ia)
     R g[Q];
     if (type != FL_FLUID) {
         if (ia.keep_walls) return;
-        if (ia.wall_u || ia.wall_rho) {
+        if (type == FL_PRESSURE) {
+            // 2 t_k rho_w [1 + 9/2 (c_k . u_w)^2 - 3/2 |u_w|^2]. Shifted
+            // storage keeps the reflection g_k = -g_out_kbar + stored in
+            // shifted values (f = g + t_k on both sides) by storing the term
+            // less 2 t_k, formed as 2 t_k (rho_w [...] - 1).
+            const double rw = ia.wall_rho ? ia.wall_rho[i] : 1.0;
+            double uw[3] = {0.0, 0.0, 0.0};
+            if (ia.wall_u) {
+                uw[0] = ia.wall_u[i];
+                uw[1] = ia.wall_u[(size_t)F.ntot + i];
+                uw[2] = ia.wall_u[2 * (size_t)F.ntot + i];
+            }
+            const double uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+            static_for<0, Q>([&](auto K) {
+                constexpr int k = K;
+                const double cu = L<Q>::cx(k) * uw[0] + L<Q>::cy(k) * uw[1] + L<Q>::cz(k) * uw[2];
+                const double e = rw * (1.0 + 4.5 * cu * cu - 1.5 * uu);
+                g[k] = R(2.0 * L<Q>::t(k) * (ST::shifted ? e - 1.0 : e));
+            });
+        } else if (ia.wall_u || ia.wall_rho) {
             const double rw = ia.wall_rho ? ia.wall_rho[i] : 1.0;
             double uw[3] = {0.0, 0.0, 0.0};
             if (ia.wall_u) {

@@ -140,9 +140,10 @@ __global__ void k_flag_types(uint8_t* fl, int nx, int ny, int nz, int geometry)
 
 // Fast-path hints of a fluid cell, from its 26 neighbours (wrapping):
 // BORDER on a box face; a wall-plane code when the non-fluid neighbours are
-// exactly the nine on one side (the fast kernels bounce those back
-// themselves); NEARWALL for any other pattern of non-fluid neighbours.
-__global__ void k_flag_hints(uint8_t* fl, int nx, int ny, int nz)
+// exactly the nine on one side and none is a pressure wall (the fast kernels
+// bounce those back themselves; `no_planes`: never, as with curved walls);
+// NEARWALL for any other pattern of non-fluid neighbours.
+__global__ void k_flag_hints(uint8_t* fl, int nx, int ny, int nz, int no_planes)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t n = (uint64_t)nx * ny * nz;
@@ -150,7 +151,7 @@ __global__ void k_flag_hints(uint8_t* fl, int nx, int ny, int nz)
     if ((fl[i] & FL_TYPE) != FL_FLUID) return;
     const int z = (int)(i % nz), y = (int)((i / nz) % ny), x = (int)(i / ((uint64_t)ny * nz));
     const bool border = x == 0 || x == nx - 1 || y == 0 || y == ny - 1 || z == 0 || z == nz - 1;
-    int total = 0, side[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // solid neighbours at d_axis = -1 / +1
+    int total = 0, pressure = 0, side[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // solid neighbours at d_axis = -1 / +1
     for (int dx = -1; dx <= 1; ++dx)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dz = -1; dz <= 1; ++dz) {
@@ -158,6 +159,7 @@ __global__ void k_flag_hints(uint8_t* fl, int nx, int ny, int nz)
                 const uint64_t j = ((uint64_t)xx * ny + yy) * nz + zz;
                 if ((fl[j] & FL_TYPE) == FL_FLUID) continue;
                 ++total;
+                pressure += (fl[j] & FL_TYPE) == FL_PRESSURE;
                 const int d[3] = {dx, dy, dz};
                 for (int a = 0; a < 3; ++a)
                     if (d[a]) ++side[a][d[a] > 0];
@@ -168,7 +170,7 @@ __global__ void k_flag_hints(uint8_t* fl, int nx, int ny, int nz)
         if (!total && nz >= 3 && (z == 0 || z == nz - 1) && x > 0 && x < nx - 1 && y > 0 && y < ny - 1) h |= FL_ZWRAP;
     } else if (total) {
         h = FL_NEARWALL;
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3 && !pressure && !no_planes; ++a)
             for (int sgn = 0; sgn < 2; ++sgn)
                 if (total == 9 && side[a][sgn] == 9) h = (uint8_t)((1 + 2 * a + sgn) << FL_PLANE_SHIFT);
     }
@@ -182,7 +184,7 @@ __global__ void k_flag_types_only(const uint8_t* fl, uint8_t* out, uint64_t n)
 }
 
 // Caller cell types: count the cells that break the rules (type not FLUID /
-// WALL / LID; a fluid cell on a box face whose axis does not wrap; a wall
+// WALL / LID / PRESSURE; a fluid cell on a box face whose axis does not wrap; a wall
 // velocity of magnitude >= 0.4 or a wall density outside (0, 10)).
 __global__ void k_check_geometry(const uint8_t* type, const double* wu, const double* wr, int nx, int ny, int nz,
                                  int wrap_x, int wrap_y, int wrap_z, unsigned long long* bad)
@@ -193,7 +195,7 @@ __global__ void k_check_geometry(const uint8_t* type, const double* wu, const do
     if (i < n) {
         const int z = (int)(i % nz), y = (int)((i / nz) % ny), x = (int)(i / ((uint64_t)ny * nz));
         const uint8_t t = type[i];
-        if (t > FL_LID) err = true;
+        if (t > FL_PRESSURE) err = true;
         if (t == FL_FLUID) {
             if (!wrap_x && (x == 0 || x == nx - 1)) err = true;
             if (!wrap_y && (y == 0 || y == ny - 1)) err = true;
@@ -208,6 +210,26 @@ __global__ void k_check_geometry(const uint8_t* type, const double* wu, const do
     }
     const unsigned long long m = __ballot(err);
     if ((threadIdx.x & 63) == 0 && m) atomicAdd(bad, (unsigned long long)__popcll(m));
+}
+
+// Curved-wall distances: count values outside (0, 1] and values other than
+// 1/2 (two counters).
+__global__ void k_check_qlink(const double* q, uint64_t n, unsigned long long* cnt)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool bad = i < n && !(q[i] > 0.0 && q[i] <= 1.0);
+    const bool curved = i < n && q[i] != 0.5;
+    const unsigned long long mb = __ballot(bad), mc = __ballot(curved);
+    if ((threadIdx.x & 63) == 0) {
+        if (mb) atomicAdd(&cnt[0], (unsigned long long)__popcll(mb));
+        if (mc) atomicAdd(&cnt[1], (unsigned long long)__popcll(mc));
+    }
+}
+
+__global__ void k_clear_hints(uint8_t* fl, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) fl[i] &= FL_TYPE;
 }
 
 __global__ void k_set_types(const uint8_t* type, uint8_t* fl, uint64_t n)
@@ -418,6 +440,7 @@ struct lbm_handle {
     uint32_t lds_local = 0;         //   kernels of local kinds
     uint32_t lds_neighbour = 0;     //   and of the kinds that reach neighbours
     bool custom_walls = false;      // wall terms set per cell (lbm_set_geometry)
+    double* qlink = nullptr;        // curved-wall distances q[k][ntot] (lbm_set_wall_distances)
     bool reverse_blocks = false;    // LBM_REVERSE_BLOCKS: step kernels visit cells in reverse order
     bool use_graph = false;         // small lattice: replay captured steps
     bool fused = false;             // one kernel per kind (fast and edge parts together)
@@ -439,6 +462,7 @@ struct lbm_handle {
         F.nz = d.nz;
         F.reverse = reverse_blocks ? 1 : 0;
         F.custom_walls = custom_walls ? 1 : 0;
+        F.qlink = qlink;
         F.lid = lid_terms(q, (int)elem_bytes(d.storage_dtype), d.lid_velocity);
         return F;
     }
@@ -819,7 +843,7 @@ static int build_tables(lbm_handle* h)
 {
     const lbm_desc* d = &h->d;
     const uint32_t g = grid_for((uint64_t)h->ntot, 256);
-    k_flag_hints<<<g, 256, 0, h->stream>>>(h->flags, d->nx, d->ny, d->nz);
+    k_flag_hints<<<g, 256, 0, h->stream>>>(h->flags, d->nx, d->ny, d->nz, h->qlink ? 1 : 0);
     unsigned long long* cnt = (unsigned long long*)h->partial;
     k_zero_u64<<<1, 1, 0, h->stream>>>(cnt);
     k_count_fluid<<<g, 256, 0, h->stream>>>(h->flags, (uint64_t)h->ntot, cnt);
@@ -1021,6 +1045,7 @@ void lbm_destroy(lbm_handle* h)
     if (h->own_flags && h->flags) (void)hipFree(h->flags);
     if (h->partial) (void)hipFree(h->partial);
     if (h->slow_list) (void)hipFree(h->slow_list);
+    if (h->qlink) (void)hipFree(h->qlink);
     if (h->fork) (void)hipEventDestroy(h->fork);
     if (h->join) (void)hipEventDestroy(h->join);
     if (h->aux) (void)hipStreamDestroy(h->aux);
@@ -1103,7 +1128,7 @@ int lbm_set_geometry(lbm_handle* h, const uint8_t* type, const double* wall_velo
     HIP_TRY(hipMemcpyAsync(&bad, cnt, sizeof(bad), hipMemcpyDeviceToHost, h->stream), "geometry check");
     HIP_TRY(hipStreamSynchronize(h->stream), "geometry check");
     if (bad)
-        return fail(LBM_EINVAL, std::to_string(bad) + " cells break the geometry rules (types FLUID/WALL/LID; "
+        return fail(LBM_EINVAL, std::to_string(bad) + " cells break the geometry rules (types FLUID/WALL/LID/PRESSURE; "
                                 "no fluid on a face that does not wrap; |u_w| < 0.4; 0 < rho_w < 10)");
     if (h->aux) HIP_TRY(hipStreamSynchronize(h->aux), "hipStreamSynchronize");
     if (h->graph) {  // its launches name the old edge-cell list
@@ -1123,6 +1148,45 @@ int lbm_set_geometry(lbm_handle* h, const uint8_t* type, const double* wall_velo
     h->steps = 0;
     h->first_nonfinite = -1;
     if (d->ptr_kind == LBM_PTR_HOST) HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return LBM_OK;
+}
+
+int lbm_set_wall_distances(lbm_handle* h, const double* q)
+{
+    if (!h || !q) return fail(LBM_EINVAL, "null argument");
+    Staging sq;
+    const void* dq;
+    const uint64_t n = (uint64_t)h->q * (uint64_t)h->ntot;
+    int rc = stage_in(h, q, sizeof(double) * n, sq, &dq);
+    if (rc) return rc;
+    unsigned long long* cnt = (unsigned long long*)h->partial;
+    k_zero_u64<<<1, 1, 0, h->stream>>>(cnt);
+    k_zero_u64<<<1, 1, 0, h->stream>>>(cnt + 1);
+    k_check_qlink<<<grid_for(n, 256), 256, 0, h->stream>>>((const double*)dq, n, cnt);
+    unsigned long long c[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(c, cnt, sizeof(c), hipMemcpyDeviceToHost, h->stream), "wall distance check");
+    HIP_TRY(hipStreamSynchronize(h->stream), "wall distance check");
+    if (c[0]) return fail(LBM_EINVAL, std::to_string(c[0]) + " wall distances outside (0, 1]");
+    if (c[1] && h->d.scheme != LBM_2POP_PULL)
+        return fail(LBM_EUNSUPPORTED, "curved walls (distances other than 1/2) need the 2Pop pull scheme, whose "
+                                      "gather reads every value the rule uses");
+    if (h->aux) HIP_TRY(hipStreamSynchronize(h->aux), "hipStreamSynchronize");
+    if (h->graph) {  // its launches name the old edge-cell list
+        HIP_TRY(hipGraphExecDestroy(h->graph), "hipGraphExecDestroy");
+        h->graph = nullptr;
+    }
+    if (!c[1]) {  // every wall half-way: the plain rule
+        if (h->qlink) HIP_TRY(hipFree(h->qlink), "hipFree");
+        h->qlink = nullptr;
+    } else {
+        if (!h->qlink) HIP_TRY(hipMalloc((void**)&h->qlink, sizeof(double) * n), "hipMalloc wall distances");
+        HIP_TRY(hipMemcpyAsync(h->qlink, dq, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream),
+                "wall distances");
+    }
+    k_clear_hints<<<grid_for((uint64_t)h->ntot, 256), 256, 0, h->stream>>>(h->flags, (uint64_t)h->ntot);
+    rc = build_tables(h);  // curved links send every wall-adjacent fluid cell to the edge kernel
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     return LBM_OK;
 }
 

@@ -26,7 +26,7 @@ COLLISIONS = {"bgk": 0, "trt": 1, "reg": 2, "rr": 3,
 DTYPES = {"f64": 0, "f32": 1, "f16": 2}
 LAYOUTS = {"soa": 0, "aos": 1}
 GEOMETRIES = {"cavity": 0, "periodic": 1, "channel": 2}
-FLUID, WALL, LID = 0, 1, 2
+FLUID, WALL, LID, PRESSURE = 0, 1, 2, 3
 
 
 class LBMError(RuntimeError):
@@ -66,7 +66,7 @@ class BatchOpts(ctypes.Structure):
 
 SYMBOLS = [
     "lbm_desc_default", "lbm_required_bytes", "lbm_create", "lbm_create_ex", "lbm_destroy",
-    "lbm_init_equilibrium", "lbm_set_geometry", "lbm_step", "lbm_macroscopic", "lbm_get_populations", "lbm_get_populations_at",
+    "lbm_init_equilibrium", "lbm_set_geometry", "lbm_set_wall_distances", "lbm_step", "lbm_macroscopic", "lbm_get_populations", "lbm_get_populations_at",
     "lbm_set_populations",
     "lbm_get_flags", "lbm_invariants", "lbm_invariants_noalloc", "lbm_neighbor_index", "lbm_get_info", "lbm_lattice", "lbm_device_copy",
     "lbm_sync", "lbm_stream_copy", "lbm_pattern_copy",
@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
     L.lbm_destroy.restype = None
     L.lbm_init_equilibrium.argtypes = [P, P, P]
     L.lbm_set_geometry.argtypes = [P, P, P, P]
+    L.lbm_set_wall_distances.argtypes = [P, P]
     L.lbm_step.argtypes = [P, I]
     L.lbm_macroscopic.argtypes = [P, P, P]
     L.lbm_get_populations.argtypes = [P, P]
@@ -300,12 +301,18 @@ class Lattice:
         check(lib().lbm_init_equilibrium(self.h, _ptr(r), _ptr(v)))
 
     def set_geometry(self, cell_types, wall_velocity=None, wall_density=None) -> None:
-        """Caller cell types (uint8 FLUID / WALL / LID per cell) with per-cell
+        """Caller cell types (uint8 FLUID / WALL / LID / PRESSURE per cell) with per-cell
         wall velocity [3][Ntot] and wall density [Ntot] of the wall cells."""
         t = _dev(cell_types, torch.uint8, self.ntot, self.device)
         wu = _dev(wall_velocity, torch.float64, 3 * self.ntot, self.device)
         wr = _dev(wall_density, torch.float64, self.ntot, self.device)
         check(lib().lbm_set_geometry(self.h, _ptr(t), _ptr(wu), _ptr(wr)))
+
+    def set_wall_distances(self, q) -> None:
+        """Curved walls: q[k][Ntot], the wall's fraction of the link from each
+        fluid cell x to its wall neighbour x - c_k (1/2: half-way)."""
+        t = _dev(q, torch.float64, self.q * self.ntot, self.device)
+        check(lib().lbm_set_wall_distances(self.h, _ptr(t)))
 
     def sync(self) -> None:
         check(lib().lbm_sync(self.h))
