@@ -440,32 +440,93 @@ def traffic_run(cav):
         torch.cuda.empty_cache()
 
 
-def cpu_baseline(cav, budget_s: float = 12.0, max_steps: int = 20, single_budget_s: float = 8.0):
-    """The FP64 oracle (2Pop, BGK) on the host cores, on the same 256^3
-    cavity, timed over as many whole steps as fit in about budget_s; then the
-    same on one thread (at least one whole step, about single_budget_s)."""
-    import oracle as O
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    cfg = O.Config(q=19, nx=cav.n, ny=cav.n, nz=cav.n, model=O.BGK, omega=cav.omega, u_lid=(cav.u_lid, 0, 0))
-    sim = O.Simulation(cfg, "2pop")
-    O.set_threads(threads)
-    sim.step(1)  # first touch of the pages
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    def timed(budget, cap):
+
+def cpu_baseline(cav, budget_s: float = 6.0, max_steps: int = 20, single_budget_s: float = 4.0):
+    """The FP64 oracle on the host cores (OpenMP over cells), on bounded
+    samples of every workload (whole steps, one to a few per case, about
+    30 s in all on 16 threads): the headline case (256^3 cavity, 2Pop pull
+    BGK) as `value`, then the 32^3 correctness cavity (100 steps), the nine
+    scheme x collision runs of the 256^3 cavity (one step each), D3Q27 RR AA
+    on a 40^3 cavity (the oracle's RR takes seconds per million cells; the
+    workload's 512^3 would need 29 GB of FP64 host memory per array), the
+    256^3 Taylor-Green AA run and the 512-cavity ensemble stepped cavity by
+    cavity; one thread on the headline case and the small cavity."""
+    import numpy as np
+    import oracle as O
+    from paper_2010_11751_amd import workloads as W
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    O.set_threads(threads)
+
+    def timed(sim, fluid, budget, cap, first=True):
+        if first:
+            sim.step(1)  # first touch of the pages
         n, t0 = 0, time.perf_counter()
         while n < cap and (n == 0 or (time.perf_counter() - t0) < budget):
             sim.step(1)
             n += 1
-        return n, time.perf_counter() - t0
-    n, dt = timed(budget_s, max_steps)
+        dt = time.perf_counter() - t0
+        return round(fluid * n / dt / 1e6, 3), n, round(dt, 2)
+
+    def cavity_cfg(n, q=19, model=O.BGK, omega=cav.omega, u=cav.u_lid):
+        return O.Config(q=q, nx=n, ny=n, nz=n, model=model, omega=omega, u_lid=(u, 0.0, 0.0))
+
+    t_all = time.perf_counter()
+    sim = O.Simulation(cavity_cfg(cav.n), HEAD_SCHEME)
+    head, n, dt = timed(sim, cav.fluid_cells, budget_s, max_steps)
     O.set_threads(1)
-    n1, dt1 = timed(single_budget_s, max_steps)
+    head1, n1, dt1 = timed(sim, cav.fluid_cells, single_budget_s, max_steps, first=False)
     O.set_threads(threads)
     del sim
-    return {"value": round(cav.fluid_cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{n} whole 2Pop BGK FP64 steps of the 256^3 cavity ({dt:.1f} s), OpenMP over cells",
-            "single_core": {"value": round(cav.fluid_cells * n1 / dt1 / 1e6, 3), "unit": "MLUPS", "cores": 1,
-                            "sample": f"{n1} whole steps ({dt1:.1f} s) on one thread"}}
+    per = {}
+    small = W.CAVITY_SMALL
+    sim = O.Simulation(cavity_cfg(small.n, omega=small.omega, u=small.u_lid), "2pop")
+    per["cavity_32_bgk_2pop_100_steps"] = timed(sim, small.fluid_cells, 1e9, 100, first=False)[0]
+    O.set_threads(1)
+    sim = O.Simulation(cavity_cfg(small.n, omega=small.omega, u=small.u_lid), "2pop")
+    per["cavity_32_bgk_2pop_100_steps_1_thread"] = timed(sim, small.fluid_cells, 1e9, 100, first=False)[0]
+    O.set_threads(threads)
+    for scheme in ("2pop", "swap", "aa"):
+        for coll in ("bgk", "trt", "reg"):
+            sim = O.Simulation(cavity_cfg(cav.n, model=O.MODELS[coll]), scheme)
+            per[f"cavity_256_{scheme}_{coll}"] = timed(sim, cav.fluid_cells, 0.0, 1)[0]
+            del sim
+    c3 = W.CAVITY_512
+    sim = O.Simulation(cavity_cfg(40, q=27, model=O.RR, omega=c3.omega, u=c3.u_lid), "aa")
+    per["cavity_40_d3q27_rr_aa (the 512^3 workload's case on 40^3)"] = timed(sim, 38 ** 3, 0.0, 2)[0]
+    del sim
+    n_tg = W.TGV_N
+    u0 = W.taylor_green_velocity(n_tg, n_tg, n_tg, W.TGV_U0)
+    sim = O.Simulation(O.Config(q=19, nx=n_tg, ny=n_tg, nz=n_tg, geometry=O.PERIODIC, omega=W.omega_from_nu(W.TGV_NU)),
+                       "aa", u=u0)
+    del u0
+    per["taylor_green_256_aa"] = timed(sim, n_tg ** 3, 0.0, 1)[0]
+    del sim
+    members = W.ensemble(512)
+    sims = [O.Simulation(O.Config(q=19, nx=m.n, ny=m.n, nz=m.n, model=O.TRT, omega=m.omega,
+                                  u_lid=(m.u_lid, 0.0, 0.0)), "aa") for m in members]
+    fluid = sum((m.n - 2) ** 3 for m in members)
+    t0 = time.perf_counter()
+    for _ in range(2):
+        for sm in sims:
+            sm.step(1)
+    per["ensemble_512_trt_aa_serial"] = round(fluid * 2 / (time.perf_counter() - t0) / 1e6, 3)
+    del sims
+    return {"value": head, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{n} whole {HEAD_SCHEME} BGK FP64 steps of the 256^3 cavity ({dt:.1f} s), OpenMP over cells",
+            "single_core": {"value": head1, "unit": "MLUPS", "cores": 1,
+                            "sample": f"{n1} whole steps ({dt1:.1f} s) on one thread"},
+            "per_workload_mlups": per,
+            "total_s": round(time.perf_counter() - t_all, 1)}
 
 
 def main():
