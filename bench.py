@@ -170,6 +170,44 @@ def pattern_probe(cav, reps: int = 20):
     return rows
 
 
+def mall_probe(reps: int = 20):
+    """The step kernels' memory patterns on footprints around the 256 MB
+    last-level cache (MALL): 19 FP64 streams of N^3 values (SoA), the local
+    pattern in place in one array (the AA even step), the local and pull
+    patterns between two arrays (2Pop), for N = 64 .. 256. GB/s of moved
+    bytes, 2 x 19 x 8 B per cell."""
+    import torch
+    from paper_2010_11751_amd import lbm
+    rows = []
+    for n3 in (64, 80, 96, 112, 128, 144, 160, 192, 256):
+        n = n3 ** 3
+        stride = (n + 1023) // 1024 * 1024
+        shift = (n3, n3)
+        size = 19 * stride + 2 * lbm.pattern_halo(0, shift)
+        a = torch.zeros(size, dtype=torch.float64, device="cuda")
+        b = torch.zeros_like(a)
+        for label, dst, pattern in (("one_array_local", a, 0), ("two_arrays_local", b, 0), ("two_arrays_pull", b, 1)):
+            def go():
+                lbm.pattern_copy(dst, a, n, stride, 0, pattern, 1, 65536, shift)
+            go()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                go()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            arrays = 1 if dst is a else 2
+            rows.append({"n": n3, "pattern": label, "footprint_mb": round(arrays * 19 * 8 * n / 2 ** 20, 1),
+                         "gbs": round(2 * 19 * 8 * n / (ms * 1e-3) / 1e9, 1)})
+            print(f"# mall probe {rows[-1]}", file=sys.stderr, flush=True)
+        del a, b
+        torch.cuda.empty_cache()
+    return rows
+
+
 def run_case(scheme, coll, dtype, steps, warmup, cav, reps=1):
     """One handle; `reps` timed runs of `steps` steps each (the first after
     `warmup` untimed steps); the median run is reported."""
@@ -356,49 +394,110 @@ def domain_sweep():
     print(json.dumps({"domain_sweep": rows, "dtype": "f64", "lattice": "D3Q19", "layout": "SoA"}), flush=True)
 
 
-def validation():
+def validation(re=100.0, u=0.1, grids=(32, 64, 128), tstar=20.0, scheme="aa", coll="bgk"):
     """Self-convergence of the lid-driven cavity (Sec. 3.1 validation case;
-    the spectral and experimental reference data are not available): Re 100,
-    lid 0.1, FP64 AA BGK, M = 32 / 64 / 128 fluid cells per edge (cell
-    centres of the coarse grid are midpoints of fine ones), after 20 lid
-    traversals. Centreline u_x(z) and u_z(x) through the cavity centre (the
-    four nearest cell columns averaged); differences between successive
-    grids, with the coarse values compared to pair averages of the fine."""
+    the spectral and experimental reference data are not available): FP64
+    D3Q19, M fluid cells per edge on nested grids (cell centres of the coarse
+    grid are midpoints of fine ones), lid u along +x, nu = u M / Re, run to
+    t = tstar M / u. Centreline u_x(z) and u_z(x) through the cavity centre
+    (the four nearest cell columns averaged), their change over the last
+    tenth of the run (steadiness), and the differences between successive
+    grids with the coarse values compared to pair averages of the fine."""
     import math
     import numpy as np
     from paper_2010_11751_amd import lbm, workloads as W
-    re, u, tstar = 100.0, 0.1, 20.0
     prof = {}
-    for m in (32, 64, 128):
+    for m in grids:
         n = m + 2
-        sim = lbm.Lattice(19, n, scheme="aa", collision="bgk", omega=W.omega_from_nu(u * m / re), u_lid=u)
+        sim = lbm.Lattice(19, n, scheme=scheme, collision=coll, omega=W.omega_from_nu(u * m / re), u_lid=u)
         steps = int(round(tstar * m / u))
         steps += steps % 2
-        sim.step(steps)
-        _, v = sim.macroscopic()
-        v = v.cpu().numpy().reshape(3, n, n, n) / u
-        c = (m // 2, m // 2 + 1)
-        ux = np.mean([v[0, a, b, 1:n - 1] for a in c for b in c], axis=0)
-        uz = np.mean([v[2, 1:n - 1, b, d] for b in c for d in c], axis=0)
+        chunk = max(2, (steps // 20) // 2 * 2)
+
+        def centrelines():
+            _, v = sim.macroscopic()
+            v = v.cpu().numpy().reshape(3, n, n, n) / u
+            c = (m // 2, m // 2 + 1)
+            ux = np.mean([v[0, a, b, 1:n - 1] for a in c for b in c], axis=0)
+            uz = np.mean([v[2, 1:n - 1, b, d] for b in c for d in c], axis=0)
+            return ux, uz
+        done, prev = 0, None
+        t0 = time.perf_counter()
+        while done < steps:
+            k = min(chunk, steps - done)
+            sim.step(k)
+            done += k
+            if steps - done <= steps // 10 and prev is None:
+                prev = centrelines()
+            sim.sync()
+            print(f"# validation Re={re:g} M={m}: {done}/{steps} steps, {time.perf_counter() - t0:.0f} s",
+                  file=sys.stderr, flush=True)
+        ux, uz = centrelines()
+        m_, _ = sim.invariants()
+        finite = bool(np.isfinite(ux).all() and np.isfinite(uz).all() and m_ == m_)
+        drift = float(max(np.abs(ux - prev[0]).max(), np.abs(uz - prev[1]).max())) if prev is not None else None
         sim.close()
-        prof[m] = (ux, uz, steps)
-        print(f"# validation M={m}: {steps} steps, min u_x/U {ux.min():.5f}, max u_z/U {uz.max():.5f}",
+        prof[m] = (ux, uz, steps, drift, finite)
+        print(f"# validation M={m}: min u_x/U {ux.min():.5f}, max u_z/U {uz.max():.5f}, drift {drift}",
               file=sys.stderr, flush=True)
 
     def coarsen(a):
         return 0.5 * (a[0::2] + a[1::2])
-    out = {"workload": "D3Q19 lid-driven cavity, Re 100, u_lid 0.1, FP64 AA BGK, t = 20 M / u_lid", "grids": {}}
-    for m in (32, 64, 128):
-        ux, uz, steps = prof[m]
-        out["grids"][m] = {"steps": steps, "min_ux": round(float(ux.min()), 6), "max_uz": round(float(uz.max()), 6),
-                           "min_uz": round(float(uz.min()), 6)}
+    out = {"workload": f"D3Q19 lid-driven cavity, Re {re:g}, u_lid {u}, FP64 {scheme} {coll}, t = {tstar:g} M / u_lid",
+           "grids": {}}
+    for m in grids:
+        ux, uz, steps, drift, finite = prof[m]
+        out["grids"][m] = {"steps": steps, "finite": finite, "min_ux": round(float(ux.min()), 6),
+                           "max_uz": round(float(uz.max()), 6), "min_uz": round(float(uz.min()), 6),
+                           "last_tenth_max_change": drift,
+                           "ux_centreline": [round(float(x), 6) for x in ux[:: max(1, m // 32)]],
+                           "uz_centreline": [round(float(x), 6) for x in uz[:: max(1, m // 32)]]}
     for key, idx in (("ux", 0), ("uz", 1)):
-        d1 = float(np.abs(prof[32][idx] - coarsen(prof[64][idx])).max())
-        d2 = float(np.abs(prof[64][idx] - coarsen(prof[128][idx])).max())
-        out[f"{key}_max_diff_32_64"] = d1
-        out[f"{key}_max_diff_64_128"] = d2
-        out[f"{key}_observed_order"] = round(math.log2(d1 / d2), 3)
+        diffs = []
+        for a, b in zip(grids[:-1], grids[1:]):
+            d = float(np.abs(prof[a][idx] - coarsen(prof[b][idx])).max())
+            out[f"{key}_max_diff_{a}_{b}"] = d
+            diffs.append(d)
+        if len(diffs) >= 2 and diffs[-1] > 0:
+            out[f"{key}_observed_order"] = round(math.log2(diffs[-2] / diffs[-1]), 3)
     print(json.dumps({"validation": out}), flush=True)
+
+
+def stability(n=400, re=10000.0, steps=20000, coll="rr", scheme="aa"):
+    """The paper's turbulent case (Sec. 3.1, 3.2: recursive regularized
+    collision, Re 10000, N = 400), FP64 D3Q19, nu = u n / Re, under three
+    settings: lid 0.05 with omega_bulk = omega, lid 0.05 with the bulk
+    relaxation set to 1 (Eq. bulk: a larger bulk viscosity), and lid 0.03.
+    Each run must stay finite and keep the closed cavity's mass; a run that
+    turns non-finite is reported with the step it did so at."""
+    import math
+    from paper_2010_11751_amd import lbm, workloads as W
+    out = []
+    for u, ob in ((0.05, None), (0.05, 1.0), (0.03, None)):
+        omega = W.omega_from_nu(u * n / re)
+        sim = lbm.Lattice(19, n, scheme=scheme, collision=coll, omega=omega, u_lid=u, omega_bulk=ob)
+        m0, _ = sim.invariants()
+        rows = []
+        done, chunk = 0, 2000
+        t0 = time.perf_counter()
+        while done < steps:
+            sim.step(chunk)
+            done += chunk
+            m, e = sim.invariants()
+            rows.append({"step": done, "mass_rel_change": (m - m0) / m0, "kinetic_energy": e})
+            print(f"# stability {coll} Re={re:g} N={n} u={u} omega_bulk={ob}: step {done}, mass change "
+                  f"{(m - m0) / m0:.3e}, KE {e:.6e}, {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+            if not (math.isfinite(m) and math.isfinite(e)):
+                break
+        sim.close()
+        finite = all(math.isfinite(r["kinetic_energy"]) for r in rows)
+        out.append({"u_lid": u, "omega": round(omega, 6), "omega_bulk": ob if ob is not None else round(omega, 6),
+                    "steps": done, "lid_traversals": round(done * u / (n - 2), 3), "finite": finite,
+                    "nonfinite_at_step": None if finite else done,
+                    "max_abs_mass_rel_change": max(abs(r["mass_rel_change"]) for r in rows) if finite else None,
+                    "kinetic_energy_last": rows[-1]["kinetic_energy"] if finite else None})
+    print(json.dumps({"stability": {"workload": f"D3Q19 cavity {n}^3, {coll} FP64 {scheme}, Re {re:g}", "runs": out}}),
+          flush=True)
 
 
 def traffic_run(cav):
@@ -548,9 +647,17 @@ def main():
                     help="only the periodic 256^3 Taylor-Green workload (2Pop pull and AA; FP64 / FP32 / FP16)")
     ap.add_argument("--validation", action="store_true",
                     help="only the cavity self-convergence study (Re 100, M = 32 / 64 / 128)")
+    ap.add_argument("--validation-re1000", action="store_true",
+                    help="only the cavity self-convergence study at Re 1000 (BGK, lid 0.05, M = 64 / 128 / 256, "
+                         "t = 40 M / u_lid)")
+    ap.add_argument("--stability", action="store_true",
+                    help="only the RR stability run of the paper's turbulent case (Re 10000, N = 400, 20000 steps)")
     ap.add_argument("--pattern-probe", action="store_true",
                     help="only the memory-pattern probe (19 FP64 streams, SoA and blocked layouts, local / pull / "
                          "AA-odd patterns) beside the FP64 step kernels of the 256^3 cavity")
+    ap.add_argument("--mall-probe", action="store_true",
+                    help="only the memory patterns of the step kernels on footprints around the 256 MB last-level "
+                         "cache (19 FP64 streams, N = 64 .. 256, one array in place or two arrays), at 2 waves per SIMD")
     ap.add_argument("--ensemble", action="store_true",
                     help="only the 512-cavity ensemble (AA and 2Pop pull; --steps graph steps, --warmup warm-up steps)")
     ap.add_argument("--traffic", action="store_true",
@@ -580,11 +687,20 @@ def main():
     if args.validation:
         validation()
         return
+    if args.validation_re1000:
+        validation(re=1000.0, u=0.05, grids=(64, 128, 256), tstar=40.0)
+        return
+    if args.stability:
+        stability()
+        return
     if args.pattern_probe:
         rows = pattern_probe(cav)
         kernels = {f"{sch}/f64": round(run_case(sch, "bgk", "f64", 200, 20, cav, reps=3)["algorithmic_gbs"], 1)
                    for sch in ("2pop_pull", "aa", "2pop")}
         print(json.dumps({"pattern_probe": rows, "step_kernels_algorithmic_gbs": kernels}), flush=True)
+        return
+    if args.mall_probe:
+        print(json.dumps({"mall_probe": mall_probe()}), flush=True)
         return
     if args.ensemble:
         seq = max(2, min(100, args.steps // 10))
