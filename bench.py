@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
 HEAD_SCHEME = "2pop_pull"
+HEAD_LAYOUT = "blocked"  # the 19 streams of each run of 256 cells kept together (the fastest pull layout)
 KERNEL_LABEL = {"2pop_pull": "2Pop pull", "aa": "AA even/odd"}
 TRAFFIC_KEY = {"2pop_pull": "pull", "aa": "aa"}
 
@@ -41,6 +42,12 @@ def kernel_source_hash() -> str:
             with open(os.path.join(csrc, name), "rb") as f:
                 h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
+
+
+def traffic_key(r) -> str:
+    """Key of a run in profiles/hbm_traffic.md: scheme, layout (SoA unnamed), collision, storage, size."""
+    lay = "" if r.get("layout", "soa") == "soa" else "_" + r["layout"]
+    return f"{TRAFFIC_KEY[r['scheme']]}{lay}_bgk_{r['dtype']}_256"
 
 
 def stored_traffic(key: str):
@@ -208,11 +215,12 @@ def mall_probe(reps: int = 20):
     return rows
 
 
-def run_case(scheme, coll, dtype, steps, warmup, cav, reps=1):
+def run_case(scheme, coll, dtype, steps, warmup, cav, reps=1, layout="soa"):
     """One handle; `reps` timed runs of `steps` steps each (the first after
     `warmup` untimed steps); the median run is reported."""
     from paper_2010_11751_amd import lbm
-    sim = lbm.Lattice(19, cav.n, scheme=scheme, collision=coll, omega=cav.omega, u_lid=cav.u_lid, dtype=dtype)
+    sim = lbm.Lattice(19, cav.n, scheme=scheme, collision=coll, omega=cav.omega, u_lid=cav.u_lid, dtype=dtype,
+                      layout=layout)
     info = sim.info()
     runs = [time_steps(sim, steps, warmup if r == 0 else 0) for r in range(reps)]
     ms, wall = sorted(runs)[len(runs) // 2]
@@ -221,7 +229,7 @@ def run_case(scheme, coll, dtype, steps, warmup, cav, reps=1):
     fluid = info.fluid_cells
     launches = 2 if scheme == "swap" else 1
     return {
-        "scheme": scheme, "collision": coll, "dtype": dtype,
+        "scheme": scheme, "collision": coll, "dtype": dtype, "layout": layout,
         "ms_per_step": ms, "wall_s": wall,
         "mlups": fluid / (ms * 1e-3) / 1e6,
         "mlups_all_cells": info.ntot / (ms * 1e-3) / 1e6,
@@ -510,13 +518,16 @@ def traffic_run(cav):
     torch.cuda.synchronize()
     del a, b
     torch.cuda.empty_cache()
-    for scheme, dtype in (("aa", "f64"), ("aa", "f32"), ("aa", "f16"), ("2pop", "f64"), ("swap", "f64"),
-                          ("2pop_pull", "f64"), ("2pop_pull", "f32"), ("2pop_pull", "f16")):
-        sim = lbm.Lattice(19, cav.n, scheme=scheme, collision="bgk", omega=cav.omega, u_lid=cav.u_lid, dtype=dtype)
+    for scheme, dtype, layout in (("aa", "f64", "soa"), ("aa", "f32", "soa"), ("aa", "f16", "soa"),
+                                  ("2pop", "f64", "soa"), ("swap", "f64", "soa"), ("2pop_pull", "f64", "soa"),
+                                  ("2pop_pull", "f32", "soa"), ("2pop_pull", "f16", "soa"),
+                                  ("2pop_pull", "f64", "blocked"), ("2pop_pull", "f32", "blocked")):
+        sim = lbm.Lattice(19, cav.n, scheme=scheme, collision="bgk", omega=cav.omega, u_lid=cav.u_lid, dtype=dtype,
+                          layout=layout)
         sim.step(4)
         sim.sync()
         info = sim.info()
-        print(json.dumps({"traffic_run": f"{scheme}/{dtype}", "fluid_cells": info.fluid_cells,
+        print(json.dumps({"traffic_run": f"{scheme}/{dtype}/{layout}", "fluid_cells": info.fluid_cells,
                           "algorithmic_bytes_per_update": info.bytes_per_update, "copy_bytes": 2 * nbytes}),
               flush=True)
         sim.close()
@@ -712,12 +723,16 @@ def main():
                           "taylor_green_256_aa": run_taylor_green(args.steps, "aa")}), flush=True)
         return
 
-    head = run_case(HEAD_SCHEME, "bgk", "f64", args.steps, args.warmup, cav, reps=args.reps)
-    print(f"# f64 {HEAD_SCHEME} bgk: {head['mlups']:.0f} MLUPS, {head['algorithmic_gbs']:.0f} GB/s", file=sys.stderr,
-          flush=True)
-    f32 = run_case(HEAD_SCHEME, "bgk", "f32", args.steps, args.warmup, cav, reps=args.reps)
-    print(f"# f32 {HEAD_SCHEME} bgk: {f32['mlups']:.0f} MLUPS, {f32['algorithmic_gbs']:.0f} GB/s", file=sys.stderr,
-          flush=True)
+    head = run_case(HEAD_SCHEME, "bgk", "f64", args.steps, args.warmup, cav, reps=args.reps, layout=HEAD_LAYOUT)
+    print(f"# f64 {HEAD_SCHEME} {HEAD_LAYOUT} bgk: {head['mlups']:.0f} MLUPS, {head['algorithmic_gbs']:.0f} GB/s",
+          file=sys.stderr, flush=True)
+    f32 = run_case(HEAD_SCHEME, "bgk", "f32", args.steps, args.warmup, cav, reps=args.reps, layout=HEAD_LAYOUT)
+    print(f"# f32 {HEAD_SCHEME} {HEAD_LAYOUT} bgk: {f32['mlups']:.0f} MLUPS, {f32['algorithmic_gbs']:.0f} GB/s",
+          file=sys.stderr, flush=True)
+    soa64 = run_case(HEAD_SCHEME, "bgk", "f64", args.steps, args.warmup, cav, reps=args.reps)
+    print(f"# f64 {HEAD_SCHEME} soa bgk: {soa64['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    soa32 = run_case(HEAD_SCHEME, "bgk", "f32", args.steps, args.warmup, cav, reps=args.reps)
+    print(f"# f32 {HEAD_SCHEME} soa bgk: {soa32['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     aa64 = run_case("aa", "bgk", "f64", args.steps, args.warmup, cav, reps=args.reps)
     print(f"# f64 aa bgk: {aa64['mlups']:.0f} MLUPS, {aa64['algorithmic_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
     aa32 = run_case("aa", "bgk", "f32", args.steps, args.warmup, cav, reps=args.reps)
@@ -764,10 +779,11 @@ def main():
 
     def roofline(r):
         achieved = r["fluid_cells"] * r["bytes_per_update"] / (r["kernel_avg_ms"] * 1e-3) / 1e9
-        traffic = stored_traffic(f"{TRAFFIC_KEY[r['scheme']]}_bgk_{r['dtype']}_256")
+        traffic = stored_traffic(traffic_key(r))
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                "kernel": "k_step<19,BGK," + r["dtype"] + ",SoA," + KERNEL_LABEL[r["scheme"]] + ">",
+                "kernel": "k_step<19,BGK," + r["dtype"] + "," + {"soa": "SoA", "blocked": "blocked"}[r["layout"]] + ","
+                          + KERNEL_LABEL[r["scheme"]] + ">",
                 "bytes_per_launch": r["fluid_cells"] * r["bytes_per_update"],
                 "frac_of_copy": round(achieved / copy_gbs, 4)}
 
@@ -792,8 +808,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "D3Q19 lid-driven cavity 256^3 incl. walls, Re=1000, u_lid=0.05, "
-                               "BGK, two-population scheme in pull form, SoA, FP64 populations",
-                   "scheme": HEAD_SCHEME,
+                               "BGK, two-population scheme in pull form, blocked layout (the 19 streams of each "
+                               "run of 256 cells together), FP64 populations",
+                   "scheme": HEAD_SCHEME, "layout": HEAD_LAYOUT,
                    "cells": cav.cells, "fluid_cells": cav.fluid_cells, "omega": round(cav.omega, 6),
                    "parallelism": "single GPU"},
         "hbm_gbs": round(head["algorithmic_gbs"], 1),
@@ -801,6 +818,9 @@ def main():
         "fp32_shifted": {"value": round(f32["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(f32["ms_per_step"], 5),
                          "hbm_gbs": round(f32["algorithmic_gbs"], 1), "speedup_vs_f64": round(f32["mlups"] / head["mlups"], 3),
                          "roofline": roofline(f32)},
+        "soa_layout": {d: {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
+                           "hbm_gbs": round(r["algorithmic_gbs"], 1), "roofline": roofline(r)}
+                       for d, r in (("f64", soa64), ("f32", soa32))},
         "aa_pattern": {d: {"value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
                            "hbm_gbs": round(r["algorithmic_gbs"], 1), "runs_ms_per_step": r["runs_ms_per_step"],
                            "roofline": roofline(r)} for d, r in (("f64", aa64), ("f32", aa32))},
@@ -814,7 +834,7 @@ def main():
     }
     print(json.dumps(out), flush=True)
     if args.jsonl:
-        write_records(args.jsonl, out, (head, f32, aa64, aa32), copy_gbs)
+        write_records(args.jsonl, out, (head, f32, soa64, soa32, aa64, aa32), copy_gbs)
 
 
 def write_records(path, out, heads, copy_gbs):

@@ -103,7 +103,13 @@ enum lbm_collision {
     LBM_BGK_NW4 = 4, LBM_RM = 5, LBM_HM = 6, LBM_CM = 7, LBM_CHM = 8, LBM_K = 9
 };
 enum lbm_dtype { LBM_F64 = 0, LBM_F32_SHIFTED = 1, LBM_F16_SHIFTED = 2 };
-enum lbm_layout { LBM_SOA = 0, LBM_AOS = 1 };
+/* LBM_SOA pop[k][N] and LBM_AOS pop[N][Q] are the layouts of Sec. 2.3.
+ * LBM_BLOCKED keeps the Q streams of each run of 256 cells together (value
+ * (k, i) at ((i / 256) Q + k) 256 + i mod 256, after whole blocks of padding):
+ * an array-of-structures-of-arrays that keeps every stream access of a wave
+ * contiguous while a block of cells touches one contiguous region; population
+ * arrays of at most 4 GiB. Results are identical in every layout. */
+enum lbm_layout { LBM_SOA = 0, LBM_AOS = 1, LBM_BLOCKED = 2 };
 enum lbm_geometry { LBM_CAVITY = 0, LBM_PERIODIC = 1, LBM_CHANNEL = 2 };
 enum lbm_flag { LBM_FLUID = 0, LBM_WALL = 1, LBM_LID = 2, LBM_PRESSURE = 3 };
 enum lbm_ptr_kind { LBM_PTR_DEVICE = 0, LBM_PTR_HOST = 1 };

@@ -185,6 +185,7 @@ hipError_t launch_tu(const Launch& L, hipStream_t s, LaunchFnPtr moment_space)
 {
     if (L.layout == LAYOUT_SOA) return launch_layout<Q, ST, LAYOUT_SOA>(L, s, moment_space);
     if (L.layout == LAYOUT_AOS) return launch_layout<Q, ST, LAYOUT_AOS>(L, s, moment_space);
+    if (L.layout == LAYOUT_BLOCKED) return launch_layout<Q, ST, LAYOUT_BLOCKED>(L, s, moment_space);
     return hipErrorInvalidValue;
 }
 
@@ -193,6 +194,7 @@ hipError_t launch_tu_moment_space(const Launch& L, hipStream_t s)
 {
     if (L.layout == LAYOUT_SOA) return launch_layout_moment_space<Q, ST, LAYOUT_SOA>(L, s);
     if (L.layout == LAYOUT_AOS) return launch_layout_moment_space<Q, ST, LAYOUT_AOS>(L, s);
+    if (L.layout == LAYOUT_BLOCKED) return launch_layout_moment_space<Q, ST, LAYOUT_BLOCKED>(L, s);
     return hipErrorInvalidValue;
 }
 

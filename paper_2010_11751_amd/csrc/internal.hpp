@@ -30,7 +30,12 @@ enum : uint8_t {
     FL_SLOW = FL_BORDER | FL_NEARWALL,
 };
 
-enum Layout { LAYOUT_SOA = 0, LAYOUT_AOS = 1 };
+enum Layout { LAYOUT_SOA = 0, LAYOUT_AOS = 1, LAYOUT_BLOCKED = 2 };
+// Cells per block of the blocked layout (all Q streams of a block together).
+#ifndef LBM_BLOCK_CELLS
+#define LBM_BLOCK_CELLS 256
+#endif
+constexpr uint32_t kBlockCells = LBM_BLOCK_CELLS;
 // KIND_PULL_Z, KIND_AA_ODD_Z: the fast parts of the pull and AA odd kernels
 // for lattices with FL_ZWRAP cells.
 enum Kind {

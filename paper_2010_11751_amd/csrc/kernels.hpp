@@ -43,7 +43,12 @@ using real_t = typename ST::R;
 // of a cell cost a single address register. The SoA array carries a halo of
 // padding around its streams (see the runtime), so a shifted access i + d for
 // any cell of the box stays inside the allocation; lanes that will not store
-// may therefore load speculatively without clamping.
+// may therefore load speculatively without clamping. The blocked layout keeps
+// the Q streams of each run of kBlockCells cells together: value (k, j) at
+// ((j / B) Q + k) B + j mod B, counted from the allocation's start, where
+// cell i sits at j = i + P and P, whole blocks of padding that cover the
+// largest neighbour offset, is passed in `stride`; offsets are 32-bit (the
+// runtime keeps such arrays below 4 GiB).
 template <class ST, int LAYOUT, int Q, bool STREAM = false>
 struct Acc {
     using T = typename ST::T;
@@ -54,6 +59,11 @@ struct Acc {
         if constexpr (LAYOUT == LAYOUT_SOA) {
             char* b = reinterpret_cast<char*>(base + (int64_t)k * stride + d);
             return reinterpret_cast<T*>(b + (uint32_t)(i * (uint32_t)sizeof(T)));
+        } else if constexpr (LAYOUT == LAYOUT_BLOCKED) {
+            constexpr uint32_t B = kBlockCells;
+            const uint32_t j = i + (uint32_t)(d + stride);
+            const uint32_t idx = (j & ~(B - 1)) * (uint32_t)Q + (uint32_t)k * B + (j & (B - 1));
+            return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T));
         } else {
             return base + ((int64_t)i + d) * Q + k;
         }
@@ -73,11 +83,11 @@ struct Acc {
         if constexpr (STREAM && LBM_NT_STORES) __builtin_nontemporal_store(v, ptr_shift(i, k, d));
         else *ptr_shift(i, k, d) = v;
     }
-    // Speculative load at i + d for the fast path: SoA relies on the halo;
-    // AoS (no halo) clamps the cell index into the box.
+    // Speculative load at i + d for the fast path: SoA and the blocked layout
+    // rely on their padding; AoS (no halo) clamps the cell index into the box.
     __device__ __forceinline__ real_t<ST> ld_fast(uint32_t i, int k, int64_t d, uint32_t ntot) const
     {
-        if constexpr (LAYOUT == LAYOUT_SOA) {
+        if constexpr (LAYOUT == LAYOUT_SOA || LAYOUT == LAYOUT_BLOCKED) {
             return real_t<ST>(raw_ld_shift(i, k, d));
         } else {
             const int64_t j = (int64_t)i + d;
@@ -86,7 +96,7 @@ struct Acc {
     }
     __device__ __forceinline__ T raw_ld_fast(uint32_t i, int k, int64_t d, uint32_t ntot) const
     {
-        if constexpr (LAYOUT == LAYOUT_SOA) {
+        if constexpr (LAYOUT == LAYOUT_SOA || LAYOUT == LAYOUT_BLOCKED) {
             return raw_ld_shift(i, k, d);
         } else {
             const int64_t j = (int64_t)i + d;

@@ -114,6 +114,19 @@ LidTerms lbm::lid_terms(int q, int elem_bytes, const double u[3])
 
 namespace {
 
+// Blocked layout: padding cells before cell 0 (whole blocks covering the
+// largest neighbour offset) and the values of the whole array.
+int64_t blocked_pad(int ny, int nz)
+{
+    const int64_t h = (int64_t)ny * nz + nz + 1;
+    return (h + kBlockCells - 1) / kBlockCells * kBlockCells;
+}
+uint64_t blocked_values(int64_t ntot, int ny, int nz, int q)
+{
+    const uint64_t cells = (uint64_t)((ntot + kBlockCells - 1) / kBlockCells * kBlockCells + 2 * blocked_pad(ny, nz));
+    return cells * (uint64_t)q;
+}
+
 double trt_omega_minus(double omega, double lambda)
 {
     return 1.0 / (0.5 + lambda / (1.0 / omega - 0.5));
@@ -524,7 +537,9 @@ static int validate(const lbm_desc* d)
     if (d->collision == LBM_K && d->lattice != 19)
         return fail(LBM_EUNSUPPORTED, "the cumulant model is defined on D3Q19 only");
     if (d->storage_dtype < LBM_F64 || d->storage_dtype > LBM_F16_SHIFTED) return fail(LBM_EINVAL, "unknown storage dtype");
-    if (d->layout != LBM_SOA && d->layout != LBM_AOS) return fail(LBM_EINVAL, "unknown layout");
+    if (d->layout != LBM_SOA && d->layout != LBM_AOS && d->layout != LBM_BLOCKED) return fail(LBM_EINVAL, "unknown layout");
+    if (d->layout == LBM_BLOCKED && blocked_values(n, d->ny, d->nz, d->lattice) * elem_bytes(d->storage_dtype) >= (1ull << 32))
+        return fail(LBM_EUNSUPPORTED, "blocked layout above 4 GiB per population array is not supported");
     if (d->geometry < LBM_CAVITY || d->geometry > LBM_CHANNEL) return fail(LBM_EINVAL, "unknown geometry");
     if (d->ptr_kind != LBM_PTR_DEVICE && d->ptr_kind != LBM_PTR_HOST) return fail(LBM_EINVAL, "unknown pointer kind");
     if (!(d->omega > 0.0 && d->omega < 2.0)) return fail(LBM_EINVAL, "omega must lie in (0, 2)");
@@ -551,7 +566,8 @@ int lbm_required_bytes(const lbm_desc* d, size_t out[3])
     const size_t pop = d->layout == LBM_SOA
                            ? ((size_t)(soa_stride(n) + kMaxStridePad) * d->lattice +
                               2 * (size_t)soa_halo(d->ny, d->nz)) * s
-                           : (size_t)n * d->lattice * s;
+                           : d->layout == LBM_BLOCKED ? (size_t)blocked_values(n, d->ny, d->nz, d->lattice) * s
+                                                      : (size_t)n * d->lattice * s;
     out[0] = pop;
     out[1] = two_arrays(d->scheme) ? pop : 0;
     out[2] = (size_t)n;
@@ -925,7 +941,9 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
     h->d = *d;
     h->q = d->lattice;
     h->ntot = (int64_t)d->nx * d->ny * d->nz;
-    h->stride = d->layout == LBM_SOA ? soa_stride(h->ntot) : h->ntot;
+    // SoA: elements between streams; blocked: the padding cells before cell 0
+    h->stride = d->layout == LBM_SOA ? soa_stride(h->ntot)
+                                     : d->layout == LBM_BLOCKED ? blocked_pad(d->ny, d->nz) : h->ntot;
     h->stream = (hipStream_t)d->stream;
     h->launch = pick_tu(d->lattice, d->storage_dtype);
     h->block = std::min(d->block_size > 0 ? d->block_size : 256, max_step_block(d->lattice, d->collision, (int)elem_bytes(d->storage_dtype)));

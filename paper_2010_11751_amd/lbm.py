@@ -24,7 +24,7 @@ SCHEMES = {"2pop": 0, "swap": 1, "aa": 2, "2pop_pull": 3}
 COLLISIONS = {"bgk": 0, "trt": 1, "reg": 2, "rr": 3,
               "nw4": 4, "rm": 5, "hm": 6, "cm": 7, "chm": 8, "k": 9}
 DTYPES = {"f64": 0, "f32": 1, "f16": 2}
-LAYOUTS = {"soa": 0, "aos": 1}
+LAYOUTS = {"soa": 0, "aos": 1, "blocked": 2}
 GEOMETRIES = {"cavity": 0, "periodic": 1, "channel": 2}
 FLUID, WALL, LID, PRESSURE = 0, 1, 2, 3
 

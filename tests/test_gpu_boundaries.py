@@ -52,7 +52,7 @@ def pressure_box(nx, ny, nz):
     return types, wu, rw
 
 
-@pytest.mark.parametrize("layout", ("soa", "aos"))
+@pytest.mark.parametrize("layout", ("soa", "aos", "blocked"))
 @pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("q,coll", [(19, "trt"), (19, "bgk"), (27, "rr")])
 def test_pressure_walls_match_oracle(lbm, q, coll, scheme, layout):
@@ -93,7 +93,7 @@ def random_qlink(q, n, seed):
     return np.random.default_rng(seed).uniform(0.05, 1.0, size=(q, n))
 
 
-@pytest.mark.parametrize("layout", ("soa", "aos"))
+@pytest.mark.parametrize("layout", ("soa", "aos", "blocked"))
 @pytest.mark.parametrize("q,coll", [(19, "bgk"), (19, "trt"), (19, "cm"), (27, "rr")])
 def test_curved_walls_match_oracle(lbm, q, coll, layout):
     """Random wall distances on every link of a moving-lid cavity, 2Pop pull:

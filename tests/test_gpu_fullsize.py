@@ -74,6 +74,22 @@ def test_cavity_256_fp64_sampled(lbm, scheme, coll):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("scheme,dtype", [("2pop_pull", "f64"), ("aa", "f64"), ("2pop_pull", "f32")])
+def test_cavity_256_blocked_layout_sampled(lbm, scheme, dtype):
+    """The blocked layout at the measured size, as the benchmark runs it."""
+    cav = W.CAVITY_256
+    print(f"case: 256^3 blocked {scheme} {dtype}", flush=True)
+    sim = lbm.Lattice(19, cav.n, scheme=scheme, collision="bgk", omega=cav.omega, u_lid=cav.u_lid, dtype=dtype,
+                      layout="blocked")
+    sim.step(3)
+    cells = sample_cells(cav.n, 48, 131)
+    tol = 1e-12 if dtype == "f64" else 2e-7
+    check_patches(sim, 19, "bgk", cav.omega, cav.u_lid, cells, cav.n, tol)
+    check_patches(sim, 19, "bgk", cav.omega, cav.u_lid, cells, cav.n, tol)
+    del sim
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("scheme", ("2pop", "aa", "2pop_pull"))
 def test_cavity_256_fp32_shifted_sampled(lbm, scheme):
     cav = W.CAVITY_256

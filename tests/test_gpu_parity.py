@@ -56,7 +56,7 @@ def test_config_small_cavity_matches_oracle(lbm):
 
 
 @pytest.mark.parametrize("q", (19, 27))
-@pytest.mark.parametrize("layout", ("soa", "aos"))
+@pytest.mark.parametrize("layout", ("soa", "aos", "blocked"))
 @pytest.mark.parametrize("coll", COLLS)
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_scheme_collision_layout_sweep(lbm, q, layout, coll, scheme):
@@ -91,7 +91,7 @@ def test_wrapping_geometries_from_a_velocity_field(lbm, q, geometry, scheme):
     assert max_err(sim.populations().cpu().numpy(), ref.populations()) <= TOL
 
 
-@pytest.mark.parametrize("layout", ("soa", "aos"))
+@pytest.mark.parametrize("layout", ("soa", "aos", "blocked"))
 @pytest.mark.parametrize("scheme", ("aa", "2pop_pull"))
 @pytest.mark.parametrize("q", (19, 27))
 def test_periodic_z_faces_on_the_fast_path(lbm, q, scheme, layout):
@@ -260,7 +260,7 @@ def test_gpu_schemes_and_layouts_agree_bit_exactly(lbm, q, coll, dtype):
     results (Sec. 2.3) on the GPU too: the collision is the same arithmetic
     in every kernel, streaming only moves values."""
     base = None
-    for layout in ("soa", "aos"):
+    for layout in ("soa", "aos", "blocked"):
         for scheme in SCHEMES:
             sim = lbm.Lattice(q, 11, 9, 13, scheme=scheme, collision=coll, omega=1.83, u_lid=0.05,
                               layout=layout, dtype=dtype)
@@ -273,7 +273,7 @@ def test_gpu_schemes_and_layouts_agree_bit_exactly(lbm, q, coll, dtype):
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
-@pytest.mark.parametrize("q,layout", [(19, "soa"), (19, "aos"), (27, "soa")])
+@pytest.mark.parametrize("q,layout", [(19, "soa"), (19, "aos"), (27, "soa"), (19, "blocked")])
 def test_captured_step_graphs_match_oracle(lbm, scheme, q, layout):
     """Small lattices replay steps from a captured HIP graph (64 steps, one
     fused kernel per kind on D3Q19 SoA). Odd eager steps in between move the

@@ -74,14 +74,15 @@ def test_shifted_cavity_every_scheme_matches_oracle(lbm, q, coll, scheme, dtype)
 @pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("q,coll", [(19, "trt"), (27, "rr")])
 def test_fp16_layouts_agree_bit_exactly(lbm, q, coll, scheme):
-    """SoA and AoS FP16 storage: same values in another order, same bits."""
+    """SoA, AoS and blocked FP16 storage: same values in another order, same bits."""
     got = {}
-    for layout in ("soa", "aos"):
+    for layout in ("soa", "aos", "blocked"):
         sim = lbm.Lattice(q, 11, 9, 13, scheme=scheme, collision=coll, omega=1.83, u_lid=0.05,
                           layout=layout, dtype="f16")
         sim.step(17)
         got[layout] = sim.populations().cpu()
     assert torch.equal(got["soa"], got["aos"])
+    assert torch.equal(got["soa"], got["blocked"])
 
 
 @pytest.mark.parametrize("scheme,first,exact", [
