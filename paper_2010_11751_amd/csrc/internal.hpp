@@ -96,6 +96,7 @@ struct Field {
     const double* qlink;   // curved walls: q[k][ntot], the wall's fraction of the link from a
                            //   fluid cell x to the wall cell x - c_k (null: all half-way)
     LidTerms lid;          // terms of lid cells (built-in geometries)
+    uint64_t zrecip;       // ceil(2^64 / nz) (nz >= 2; else 0): floor(i / nz) = high word of i * zrecip
 };
 
 // Largest block of the step kernels: the moment-space models (model >= 4)

@@ -120,6 +120,25 @@ __device__ __forceinline__ Coord cell_coord(uint32_t i, const Field& F)
     return c;
 }
 
+// Index corrections of the z-face lanes of the AA odd fast kernel in FP16. A
+// lane on a z face (a wall cell, or a fluid cell that the edge part updates)
+// never uses what it reads across that face, so it may read its own row
+// instead: +1 at z = 0, -1 at z = nz - 1. The wave then touches no cache line
+// of the neighbouring row. In FP16 a row of 256 cells spans four lines of a
+// stream, and that line of the neighbouring row added a quarter to the reads
+// of each z-shifted stream (AA odd: 361 -> 322 us per step on the 256^3
+// cavity); in FP32 and FP64 the share is an eighth and a sixteenth, and the
+// correction measured slower. z = i - nz floor(i / nz), the quotient being the
+// high word of i * ceil(2^64 / nz); F.zrecip = 0 (nz < 2) turns it off.
+__device__ __forceinline__ void face_rows(const Field& F, uint32_t i, int32_t& zp, int32_t& zm)
+{
+    if (!F.zrecip) return;
+    const uint32_t row = (uint32_t)__umul64hi((unsigned long long)i, F.zrecip);
+    const uint32_t z = i - row * (uint32_t)F.nz;
+    zp = z == 0 ? 1 : 0;
+    zm = z == (uint32_t)F.nz - 1 ? -1 : 0;
+}
+
 // Neighbour x + s*c_k. Interior cells: constant offset. Border cells: wrap
 // each coordinate (only periodic axes ever wrap for a fluid cell).
 template <int Q, int K, int SIGN>
@@ -460,11 +479,17 @@ __device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<S
         }
         // ZWRAP variant: z-face cells of a box that wraps in z reach their
         // wrapped neighbours through a per-lane index correction: +nz at
-        // z = 0 (reading z - 1, writing z - 1), -nz at z = nz - 1.
+        // z = 0 (reading z - 1, writing z - 1), -nz at z = nz - 1. FP16
+        // otherwise: z-face lanes read their own row (face_rows) and store
+        // nothing.
         int32_t zp = 0, zm = 0;
-        if (ZWRAP && (fl & FL_ZWRAP)) {
-            if (i % (uint32_t)F.nz == 0) zp = F.nz;
-            else zm = -F.nz;
+        if constexpr (ZWRAP) {
+            if (fl & FL_ZWRAP) {
+                if (i % (uint32_t)F.nz == 0) zp = F.nz;
+                else zm = -F.nz;
+            }
+        } else if constexpr (sizeof(typename ST::T) == 2) {
+            face_rows(F, i, zp, zm);
         }
         R g[Q];
         static_for<0, Q>([&](auto K) {
@@ -477,6 +502,7 @@ __device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<S
             }
         });
         issue_all(g);
+        if constexpr (!ZWRAP) zp = zm = 0;  // lanes that store are off the z faces
         if (fl & FL_PLANE) {  // pull across the wall plane: pop_k(x) + pop_kbar(x - c_k)
             static_for<0, Q>([&](auto K) {
                 constexpr int k = K;

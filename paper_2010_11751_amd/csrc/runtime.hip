@@ -417,6 +417,11 @@ int scratch_address(int device, double** out)
 
 // --- handle --------------------------------------------------------------------
 
+// ceil(2^64 / d) for d >= 2, else 0. The high word of i * ceil(2^64 / d) is
+// floor(i / d) for every 32-bit i: it exceeds i / d by less than i / 2^64 <
+// 2^-32 <= 1/d, too little to carry past the next integer.
+static uint64_t reciprocal64(int d) { return d >= 2 ? ~0ull / (uint64_t)d + 1 : 0; }
+
 // Schemes with a second population array.
 static bool two_arrays(int scheme) { return scheme == LBM_2POP || scheme == LBM_2POP_PULL; }
 
@@ -477,6 +482,7 @@ struct lbm_handle {
         F.custom_walls = custom_walls ? 1 : 0;
         F.qlink = qlink;
         F.lid = lid_terms(q, (int)elem_bytes(d.storage_dtype), d.lid_velocity);
+        F.zrecip = reciprocal64(d.nz);
         return F;
     }
     Launch base(int op) const
