@@ -32,6 +32,7 @@ HEAD_SCHEME = "2pop_pull"
 HEAD_LAYOUT = "blocked"  # the 19 streams of each run of 256 cells kept together (the fastest pull layout)
 KERNEL_LABEL = {"2pop_pull": "2Pop pull", "aa": "AA even/odd"}
 TRAFFIC_KEY = {"2pop_pull": "pull", "aa": "aa"}
+LAYOUT_NAME = {"soa": "SoA", "aos": "AoS", "blocked": "blocked"}
 
 
 def kernel_source_hash() -> str:
@@ -243,27 +244,29 @@ def run_case(scheme, coll, dtype, steps, warmup, cav, reps=1, layout="soa"):
     }
 
 
-def run_d3q27_rr(steps, warmup, scheme="aa"):
-    """512^3 D3Q27 cavity, recursive regularized, FP32-shifted SoA (Re 5000);
-    the workload names the AA pattern, and 2Pop pull runs beside it."""
+def run_d3q27_rr(steps, warmup, scheme="aa", layout="soa"):
+    """512^3 D3Q27 cavity, recursive regularized, FP32-shifted (Re 5000); the
+    workload names the AA pattern, and 2Pop pull runs beside it."""
     from paper_2010_11751_amd import lbm, workloads as W
     cav = W.CAVITY_512
-    sim = lbm.Lattice(27, cav.n, scheme=scheme, collision="rr", omega=cav.omega, u_lid=cav.u_lid, dtype="f32")
+    sim = lbm.Lattice(27, cav.n, scheme=scheme, collision="rr", omega=cav.omega, u_lid=cav.u_lid, dtype="f32",
+                      layout=layout)
     info = sim.info()
     ms, _ = time_steps(sim, steps, warmup)
     m, e = sim.invariants()
     sim.close()
     gbs = info.fluid_cells * info.bytes_per_update / (ms * 1e-3) / 1e9
-    return {"workload": f"D3Q27 lid-driven cavity 512^3, RR, FP32-shifted {scheme} SoA, Re=5000, u_lid=0.05",
+    return {"workload": f"D3Q27 lid-driven cavity 512^3, RR, FP32-shifted {scheme} {LAYOUT_NAME[layout]}, Re=5000, "
+                        "u_lid=0.05",
             "scheme": scheme,
             "mlups": round(info.fluid_cells / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
             "bytes_per_update": info.bytes_per_update, "hbm_gbs": round(gbs, 1),
             "roofline_frac": round(gbs / PEAK_HBM_GBS, 4), "steps": steps, "finite": bool(m == m and e == e)}
 
 
-def run_taylor_green(steps, scheme):
-    """256^3 periodic Taylor-Green vortex (u0 = 0.04, nu = 0.01), BGK SoA
-    under one scheme, FP64 vs FP32- and FP16-shifted storage: MLUPS,
+def run_taylor_green(steps, scheme, layout="soa"):
+    """256^3 periodic Taylor-Green vortex (u0 = 0.04, nu = 0.01), BGK under
+    one scheme and layout, FP64 vs FP32- and FP16-shifted storage: MLUPS,
     velocity relative L2 against the FP64 run, and the decay of the (k,k,k)
     mode against exp(-3 nu k^2 t)."""
     import math
@@ -275,7 +278,8 @@ def run_taylor_green(steps, scheme):
     mode = u0[0].to("cuda")
     out, ref = {}, None
     for dtype in ("f64", "f32", "f16"):
-        sim = lbm.Lattice(19, n, scheme=scheme, collision="bgk", omega=omega, geometry="periodic", dtype=dtype)
+        sim = lbm.Lattice(19, n, scheme=scheme, collision="bgk", omega=omega, geometry="periodic", dtype=dtype,
+                          layout=layout)
         sim.init_equilibrium(None, u0)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -299,7 +303,8 @@ def run_taylor_green(steps, scheme):
             r["velocity_rel_l2_vs_f64"] = float(torch.linalg.vector_norm(u - ref) / torch.linalg.vector_norm(ref))
         out[dtype] = r
     k = 2 * math.pi / n
-    return {"workload": f"D3Q19 BGK triply periodic Taylor-Green 256^3, u0=0.04, nu=0.01, {scheme} SoA",
+    return {"workload": f"D3Q19 BGK triply periodic Taylor-Green 256^3, u0=0.04, nu=0.01, {scheme} "
+                        f"{LAYOUT_NAME[layout]}",
             "scheme": scheme, "steps": steps, "analytic_exp_minus_3nuk2t": math.exp(-3 * W.TGV_NU * k * k * steps), **out}
 
 
@@ -719,7 +724,7 @@ def main():
                           "ensemble_512_pull": run_ensemble(args.steps, seq, HEAD_SCHEME, args.warmup)}), flush=True)
         return
     if args.taylor_green:
-        print(json.dumps({"taylor_green_256": run_taylor_green(args.steps, HEAD_SCHEME),
+        print(json.dumps({"taylor_green_256": run_taylor_green(args.steps, HEAD_SCHEME, HEAD_LAYOUT),
                           "taylor_green_256_aa": run_taylor_green(args.steps, "aa")}), flush=True)
         return
 
@@ -764,7 +769,7 @@ def main():
         workloads["cavity_512_d3q27_rr_f32_pull"] = run_d3q27_rr(max(args.steps // 5, 20), 10, HEAD_SCHEME)
         print(f"# d3q27 rr 512 {HEAD_SCHEME}: {workloads['cavity_512_d3q27_rr_f32_pull']['mlups']} MLUPS", file=sys.stderr,
               flush=True)
-        workloads["taylor_green_256"] = run_taylor_green(2000, HEAD_SCHEME)
+        workloads["taylor_green_256"] = run_taylor_green(2000, HEAD_SCHEME, HEAD_LAYOUT)
         workloads["taylor_green_256_aa"] = run_taylor_green(2000, "aa")
         print("# taylor-green done", file=sys.stderr, flush=True)
         workloads["ensemble_512"] = run_ensemble(1000, 100)
