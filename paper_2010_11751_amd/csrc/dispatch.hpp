@@ -23,15 +23,20 @@ hipError_t launch_step_kind(const Launch& L, hipStream_t s)
         return hipGetLastError();
     }
     const uint32_t lds = L.lds;
+    // edge part in the first L.edge_blocks blocks (kinds that have one)
+    const uint32_t* const el = L.slow_list;
+    const uint32_t ne = L.n_slow, eb = L.edge_blocks;
     switch (L.kind) {
-    case KIND_2POP: k_step<Q, MODEL, ST, LAYOUT, KIND_2POP><<<g, b, lds, s>>>(L.F, L.relax); break;
-    case KIND_SWAP_COLLIDE: k_step<Q, MODEL, ST, LAYOUT, KIND_SWAP_COLLIDE><<<g, b, lds, s>>>(L.F, L.relax); break;
-    case KIND_SWAP_STREAM: k_step<Q, BGK, ST, LAYOUT, KIND_SWAP_STREAM><<<g, b, lds, s>>>(L.F, L.relax); break;
-    case KIND_AA_EVEN: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_EVEN><<<g, b, lds, s>>>(L.F, L.relax); break;
-    case KIND_AA_ODD: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, lds, s>>>(L.F, L.relax); break;
-    case KIND_PULL: k_step<Q, MODEL, ST, LAYOUT, KIND_PULL><<<g, b, lds, s>>>(L.F, L.relax); break;
-    case KIND_PULL_Z: k_step<Q, MODEL, ST, LAYOUT, KIND_PULL_Z><<<g, b, lds, s>>>(L.F, L.relax); break;
-    case KIND_AA_ODD_Z: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_ODD_Z><<<g, b, lds, s>>>(L.F, L.relax); break;
+    case KIND_2POP: k_step<Q, MODEL, ST, LAYOUT, KIND_2POP><<<g, b, lds, s>>>(L.F, L.relax, el, ne, eb); break;
+    case KIND_SWAP_COLLIDE:
+        k_step<Q, MODEL, ST, LAYOUT, KIND_SWAP_COLLIDE><<<g, b, lds, s>>>(L.F, L.relax, nullptr, 0, 0);
+        break;
+    case KIND_SWAP_STREAM: k_step<Q, BGK, ST, LAYOUT, KIND_SWAP_STREAM><<<g, b, lds, s>>>(L.F, L.relax, el, ne, eb); break;
+    case KIND_AA_EVEN: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_EVEN><<<g, b, lds, s>>>(L.F, L.relax, nullptr, 0, 0); break;
+    case KIND_AA_ODD: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_ODD><<<g, b, lds, s>>>(L.F, L.relax, el, ne, eb); break;
+    case KIND_PULL: k_step<Q, MODEL, ST, LAYOUT, KIND_PULL><<<g, b, lds, s>>>(L.F, L.relax, el, ne, eb); break;
+    case KIND_PULL_Z: k_step<Q, MODEL, ST, LAYOUT, KIND_PULL_Z><<<g, b, lds, s>>>(L.F, L.relax, el, ne, eb); break;
+    case KIND_AA_ODD_Z: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_ODD_Z><<<g, b, lds, s>>>(L.F, L.relax, el, ne, eb); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

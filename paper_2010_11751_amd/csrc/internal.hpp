@@ -200,8 +200,9 @@ struct Launch {
     uint32_t xcd;            // STEP_BATCH: deal the tile table to the eight XCDs in contiguous parts
                              //   (grid a multiple of eight)
     const uint32_t* wave_cav;  // STEP_BATCH_SLOW: cavity of each wave of the edge-cell list
-    const uint32_t* slow_list;  // STEP_SLOW: fluid cells off the fast path
+    const uint32_t* slow_list;  // STEP_SLOW, STEP: fluid cells off the fast path
     uint32_t n_slow;
+    uint32_t edge_blocks;       // STEP: leading blocks that take slow_list (0: fast part only)
     uint32_t lds;          // STEP: dynamic LDS bytes per block (caps blocks per CU)
 };
 

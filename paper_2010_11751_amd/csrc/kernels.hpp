@@ -642,11 +642,12 @@ __device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>
     else cell_pull<Q, MODEL, ST, LAYOUT, PART, true>(F, p, i);
 }
 
-__device__ __forceinline__ uint32_t step_block(const Field& F)
+// Block b of nb fast-part blocks in the order the cells are visited.
+__device__ __forceinline__ uint32_t step_block(const Field& F, uint32_t b, uint32_t nb)
 {
-    uint32_t b = F.reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
+    b = F.reverse ? nb - 1 - b : b;
     if (LBM_XCD_REMAP) {
-        const uint32_t per = gridDim.x / 8;
+        const uint32_t per = nb / 8;
         if (b < per * 8) b = (b % 8) * per + b / 8;
     }
     return b;
@@ -657,11 +658,41 @@ __device__ __forceinline__ uint32_t step_block(const Field& F)
 #define LBM_STEP_ATTR(Q, ST, KIND) \
     __attribute__((amdgpu_waves_per_eu(min_step_waves(Q, (int)sizeof(typename ST::T), KIND))))
 
-// Fast part over every cell of the lattice.
-template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
-__global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) LBM_STEP_ATTR(Q, ST, KIND) k_step(Field F, RelaxD pd)
+// Kinds whose cells reach their neighbours, and so have an edge-cell part;
+// the z-wrap variants of the fast part share the edge part of their kind.
+constexpr bool has_edge_part(int kind)
 {
-    const uint32_t i = step_block(F) * blockDim.x + threadIdx.x;
+    return kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD || kind == KIND_PULL ||
+           kind == KIND_PULL_Z || kind == KIND_AA_ODD_Z;
+}
+
+constexpr int edge_kind(int kind)
+{
+    return kind == KIND_PULL_Z ? KIND_PULL : (kind == KIND_AA_ODD_Z ? KIND_AA_ODD : kind);
+}
+
+// One launch per step: the first edge_blocks blocks take the cells of the
+// edge-cell list (the edge part), the others every cell of the lattice (the
+// fast part, which leaves the listed cells alone). The two parts touch
+// disjoint memory, since every cell owns the locations it reads and writes,
+// so they need no order between them; the listed cells come first, so that
+// their scattered, latency-bound accesses overlap the streaming of the fast
+// part and the step needs no second stream.
+template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
+__global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) LBM_STEP_ATTR(Q, ST, KIND)
+    k_step(Field F, RelaxD pd, const uint32_t* __restrict__ list, uint32_t n_edge, uint32_t edge_blocks)
+{
+    if constexpr (has_edge_part(KIND)) {
+        if (blockIdx.x < edge_blocks) {
+            const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+            if (j >= n_edge) return;
+            const uint32_t i = list[F.reverse ? n_edge - 1 - j : j];
+            if (i >= F.ntot) return;
+            cell_step<Q, MODEL, ST, LAYOUT, edge_kind(KIND), PART_SLOW>(F, relax_of<real_t<ST>>(pd), i);
+            return;
+        }
+    }
+    const uint32_t i = step_block(F, blockIdx.x - edge_blocks, gridDim.x - edge_blocks) * blockDim.x + threadIdx.x;
     if (i >= F.ntot) return;
     cell_step<Q, MODEL, ST, LAYOUT, KIND, PART_FAST>(F, relax_of<real_t<ST>>(pd), i);
 }
@@ -741,7 +772,7 @@ __device__ __forceinline__ void group_step(const Field& F, const Relax<real_t<ST
 template <int Q, int MODEL, class ST, int KIND, int CPT>
 __global__ void __launch_bounds__(256) LBM_STEP_ATTR(Q, ST, KIND) k_step_vec(Field F, RelaxD pd)
 {
-    const uint32_t i0 = (step_block(F) * blockDim.x + threadIdx.x) * CPT;
+    const uint32_t i0 = (step_block(F, blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) * CPT;
     if (i0 + CPT > F.ntot) return;  // a ragged tail is in the near-wall list
     group_step<Q, MODEL, ST, KIND, CPT>(F, relax_of<real_t<ST>>(pd), i0);
 }
@@ -751,7 +782,7 @@ __global__ void __launch_bounds__(256) LBM_STEP_ATTR(Q, ST, KIND) k_step_vec(Fie
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
 __global__ void __launch_bounds__(max_step_block(Q, MODEL, (int)sizeof(typename ST::T))) LBM_STEP_ATTR(Q, ST, KIND) k_step_all(Field F, RelaxD pd)
 {
-    const uint32_t i = step_block(F) * blockDim.x + threadIdx.x;
+    const uint32_t i = step_block(F, blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= F.ntot) return;
     cell_step<Q, MODEL, ST, LAYOUT, KIND, PART_ALL>(F, relax_of<real_t<ST>>(pd), i);
 }

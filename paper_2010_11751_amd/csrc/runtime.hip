@@ -630,18 +630,27 @@ static int run_kind(lbm_handle* h, int kind)
         return run(h, L);
     }
     const int cpt = h->cpt;
-    if (cpt > 1) {  // the vector kernels are compiled for blocks of at most 256
-        L.block = std::min(h->block, 256);
-        L.grid = grid_for(((uint64_t)h->ntot + cpt - 1) / cpt, L.block);
+    const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD || kind == KIND_PULL;
+    const uint32_t n_slow = zwrap_kind(kind) ? h->n_slow_z : h->n_slow;
+    if (cpt == 1) {  // one launch, the edge part in the leading blocks
+        L.kind = fast_kind(h, kind);
+        if (neighbours && n_slow > 0) {
+            L.slow_list = zwrap_kind(kind) ? h->slow_list_z : h->slow_list;
+            L.n_slow = n_slow;
+            L.edge_blocks = grid_for(n_slow, L.block);
+            L.grid += L.edge_blocks;
+        }
+        return run(h, L);
     }
+    // the vector kernels are compiled for blocks of at most 256
+    L.block = std::min(h->block, 256);
+    L.grid = grid_for(((uint64_t)h->ntot + cpt - 1) / cpt, L.block);
     L.kind = fast_kind(h, kind);
     int rc = run(h, L);
     if (rc) return rc;
     L.kind = kind;
     // With several cells per lane the fast part skips whole groups, so the
     // listed cells need the second launch for the local kinds as well.
-    const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD || kind == KIND_PULL;
-    const uint32_t n_slow = zwrap_kind(kind) ? h->n_slow_z : h->n_slow;
     if ((neighbours || cpt > 1) && n_slow > 0) {
         L.op = OP_STEP_SLOW;
         L.block = 256;
@@ -653,10 +662,13 @@ static int run_kind(lbm_handle* h, int kind)
     return rc;
 }
 
-// The same, with the near-wall part on a second stream so that its scattered,
-// latency-bound accesses overlap the fast part's streaming. Both parts touch
-// disjoint memory (every cell owns its locations), and the handle's stream
-// waits for the second one before the next launch.
+// The same as two launches, the edge part on a second stream so that its
+// scattered, latency-bound accesses overlap the fast part's streaming. Both
+// parts touch disjoint memory (every cell owns its locations), and the
+// handle's stream waits for the second one before the next launch. Used by
+// the kernels with several cells per lane, and on request (LBM_SPLIT_STEP)
+// in place of the single launch of run_kind, whose leading blocks overlap the
+// parts without the cross-stream wait.
 static int run_kind_overlapped(lbm_handle* h, int kind)
 {
     const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD || kind == KIND_PULL;
@@ -908,7 +920,7 @@ static int build_tables(lbm_handle* h)
             HIP_TRY(hipMemcpy(h->slow_list_z, pull.data(), sizeof(uint32_t) * pull.size(), hipMemcpyHostToDevice),
                     "slow list");
     }
-    if (h->n_slow > 0 && !h->aux && !std::getenv("LBM_NO_OVERLAP")) {
+    if (h->n_slow > 0 && !h->aux && !std::getenv("LBM_NO_OVERLAP") && (h->cpt > 1 || std::getenv("LBM_SPLIT_STEP"))) {
         HIP_TRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking), "auxiliary stream");
         HIP_TRY(hipEventCreateWithFlags(&h->fork, hipEventDisableTiming), "auxiliary stream");
         HIP_TRY(hipEventCreateWithFlags(&h->join, hipEventDisableTiming), "auxiliary stream");
