@@ -49,6 +49,20 @@ using real_t = typename ST::R;
 // cell i sits at j = i + P and P, whole blocks of padding that cover the
 // largest neighbour offset, is passed in `stride`; offsets are 32-bit (the
 // runtime keeps such arrays below 4 GiB).
+// A value rounded to the storage type. On its way into FP16 the float passes
+// an empty asm, which makes it opaque to the compiler: the operation that
+// produced it can then not be folded with the conversion into one
+// mixed-precision instruction with an FP16 result (v_fma_mixlo_f16 rounds
+// a * b + c to FP16 once, where the FP32 arithmetic followed by the
+// conversion rounds twice). Without it, two kernels holding the same float
+// could store different FP16 bits, depending on instruction selection.
+template <class ST>
+__device__ __forceinline__ typename ST::T to_storage(real_t<ST> v)
+{
+    if constexpr (sizeof(typename ST::T) == 2) asm volatile("" : "+v"(v));
+    return typename ST::T(v);
+}
+
 template <class ST, int LAYOUT, int Q, bool STREAM = false>
 struct Acc {
     using T = typename ST::T;
@@ -70,7 +84,7 @@ struct Acc {
     }
     __device__ __forceinline__ T* ptr(uint32_t i, int k) const { return ptr_shift(i, k, 0); }
     __device__ __forceinline__ real_t<ST> ld(uint32_t i, int k) const { return real_t<ST>(raw_ld(i, k)); }
-    __device__ __forceinline__ void st(uint32_t i, int k, real_t<ST> v) const { raw_st(i, k, T(v)); }
+    __device__ __forceinline__ void st(uint32_t i, int k, real_t<ST> v) const { raw_st(i, k, to_storage<ST>(v)); }
     __device__ __forceinline__ T raw_ld(uint32_t i, int k) const { return raw_ld_shift(i, k, 0); }
     __device__ __forceinline__ void raw_st(uint32_t i, int k, T v) const { raw_st_shift(i, k, 0, v); }
     __device__ __forceinline__ T raw_ld_shift(uint32_t i, int k, int64_t d) const
@@ -314,7 +328,7 @@ __device__ __forceinline__ void cell_2pop(const Field& F, const Relax<real_t<ST>
             static_for<0, Q>([&](auto K) {
                 constexpr int k = K;
                 if (!wall_to<Q, k>(fl)) {
-                    dst.raw_st_shift(i, k, offset<Q, k, 1>(F), typename ST::T(g[k]));
+                    dst.raw_st_shift(i, k, offset<Q, k, 1>(F), to_storage<ST>(g[k]));
                 } else {  // out_kbar(x) <- f_out_k + pop_k(x + c_k)
                     const R w = R(src.raw_ld_shift(i, k, offset<Q, k, 1>(F)));
                     dst.st(i, L<Q>::opp(k), g[k] + w);
@@ -516,7 +530,7 @@ __device__ __forceinline__ void cell_aa_odd(const Field& F, const Relax<real_t<S
             constexpr int k = K;
             if (!wall_to<Q, k>(fl)) {
                 const uint32_t j = S::cz(k) > 0 ? i + zm : (S::cz(k) < 0 ? i + zp : i);
-                a.raw_st_shift(j, k, offset<Q, k, 1>(F), typename ST::T(g[k]));
+                a.raw_st_shift(j, k, offset<Q, k, 1>(F), to_storage<ST>(g[k]));
             } else {  // push across the wall plane: pop_kbar(x) <- f_out_k + pop_k(x + c_k)
                 const R w = R(a.raw_ld_shift(i, k, offset<Q, k, 1>(F)));
                 a.st(i, S::opp(k), g[k] + w);
@@ -629,6 +643,148 @@ __device__ __forceinline__ void cell_pull(const Field& F, const Relax<real_t<ST>
     }
 }
 
+// ---------------------------------------------------------------------------
+// Box cavities of the built-in geometry, with every decision taken from the
+// cell's position instead of its flag byte: a cell is fluid iff
+// 1 <= x <= nx-2 (and so for y, z), its neighbour x +- c_k is a wall iff it
+// leaves that range, and a wall cell is a lid cell iff it lies in the layer
+// z = nz-1. Each direction then costs one load and one store whose address
+// is chosen per lane (neighbour slot, or the cell's own slot across a wall)
+// and the wall terms come from the lid table, so walls, faces, edges and
+// corners all stay on one branch-free path, with no flag traffic and no
+// second gather round. Used by the ensemble, whose members are such
+// cavities; ntot < 2^24 (exact float quotients below).
+
+// Lid term w_J of the table in the storage type.
+template <class ST, int J>
+__device__ __forceinline__ real_t<ST> lid_value(const Field& F)
+{
+    if constexpr (sizeof(typename ST::T) == 8) return F.lid.d[J];
+    else return F.lid.f[J];
+}
+
+struct BoxPos {
+    // lo[a]: coordinate a is 1; hi[a]: it is n_a - 2 (both for n_a = 3);
+    // top: the cell lies in the lid layer z = nz - 1.
+    bool fluid, top, lo[3], hi[3];
+};
+
+// floor(n / d) for n < 2^24 and d >= 1: the float quotient is within one of
+// the true one, and one correction step fixes it.
+__device__ __forceinline__ uint32_t udiv24(uint32_t n, uint32_t d, float rcp)
+{
+    uint32_t q = (uint32_t)((float)n * rcp);
+    const int32_t r = (int32_t)(n - q * d);
+    if (r < 0) --q;
+    else if (r >= (int32_t)d) ++q;
+    return q;
+}
+
+__device__ __forceinline__ BoxPos box_pos(const Field& F, uint32_t i, float rcp_nz, float rcp_ny)
+{
+    const uint32_t row = udiv24(i, (uint32_t)F.nz, rcp_nz);
+    const int z = (int)(i - row * (uint32_t)F.nz);
+    const uint32_t x = udiv24(row, (uint32_t)F.ny, rcp_ny);
+    const int y = (int)(row - x * (uint32_t)F.ny);
+    const int c[3] = {(int)x, y, z}, n[3] = {F.nx, F.ny, F.nz};
+    BoxPos p;
+    p.fluid = true;
+    for (int a = 0; a < 3; ++a) {
+        p.fluid = p.fluid && c[a] >= 1 && c[a] <= n[a] - 2;
+        p.lo[a] = c[a] == 1;
+        p.hi[a] = c[a] == n[a] - 2;
+    }
+    p.top = z == F.nz - 1;
+    return p;
+}
+
+// The same for a single lattice of any size (i < 2^32): the quotients from
+// the 64-bit reciprocals of nz and ny, exact for every 32-bit index.
+__device__ __forceinline__ BoxPos box_pos64(const Field& F, uint32_t i)
+{
+    const uint32_t row = (uint32_t)__umul64hi((unsigned long long)i, F.zrecip);
+    const int z = (int)(i - row * (uint32_t)F.nz);
+    const uint32_t x = (uint32_t)__umul64hi((unsigned long long)row, F.yrecip);
+    const int y = (int)(row - x * (uint32_t)F.ny);
+    const int c[3] = {(int)x, y, z}, n[3] = {F.nx, F.ny, F.nz};
+    BoxPos p;
+    p.fluid = true;
+    for (int a = 0; a < 3; ++a) {
+        p.fluid = p.fluid && c[a] >= 1 && c[a] <= n[a] - 2;
+        p.lo[a] = c[a] == 1;
+        p.hi[a] = c[a] == n[a] - 2;
+    }
+    p.top = z == F.nz - 1;
+    return p;
+}
+
+// Fluid cell: x + s*c_k is a wall.
+template <int Q, int K, int SIGN>
+__device__ __forceinline__ bool box_wall(const BoxPos& p)
+{
+    bool w = false;
+    static_for<0, 3>([&](auto A) {
+        constexpr int a = A;
+        constexpr int c = SIGN * L<Q>::c(K, a);
+        if constexpr (c > 0) w = w || p.hi[a];
+        else if constexpr (c < 0) w = w || p.lo[a];
+    });
+    return w;
+}
+
+// Fluid cell whose neighbour x + s*c_k is a wall: the stored term of that
+// wall cell in slot J, a lid term iff the wall lies in the layer z = nz - 1.
+template <int Q, int K, int SIGN, class ST, int J>
+__device__ __forceinline__ real_t<ST> box_wall_term(const Field& F, const BoxPos& p)
+{
+    if constexpr (SIGN * L<Q>::cz(K) > 0) return p.hi[2] ? lid_value<ST, J>(F) : real_t<ST>(0);
+    else return real_t<ST>(0);
+}
+
+// Pull kind for the built-in cavity of a single lattice (either layout),
+// every decision taken from the cell's position as in the box kernels below:
+// a fluid lane gathers pop_kbar(x - c_k), or its own pop_k(x) plus the wall's
+// term from the lid table across a wall, with one load per direction at an
+// address chosen per lane; wall lanes load nothing and write their terms into
+// the other array. No flag byte, no second round of loads for cells next to
+// a wall, and no edge-cell list (edges and corners take the same path). The
+// sums are those of the flag-driven pull kernel, operand for operand.
+template <int Q, int MODEL, class ST, int LAYOUT>
+__device__ __forceinline__ void box_pull_cell(const Field& F, const Relax<real_t<ST>>& rp, uint32_t i)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    using T = typename ST::T;
+    const Acc<ST, LAYOUT, Q, true> a{(T*)F.pop, F.stride};
+    const Acc<ST, LAYOUT, Q, true> o{(T*)F.out, F.stride};
+    const BoxPos p = box_pos64(F, i);
+    R g[Q];
+    static_for<0, Q>([&](auto K) { g[K] = R(0); });
+    if (p.fluid) {
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            if constexpr (k == S::rest) {
+                g[k] = a.ld(i, k);
+            } else {
+                const T* const own = a.ptr(i, k);
+                const T* const nb = a.ptr_shift(i, S::opp(k), offset<Q, k, -1>(F));
+                g[k] = R(*(box_wall<Q, k, -1>(p) ? own : nb));
+            }
+        });
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            if constexpr (k != S::rest)
+                if (box_wall<Q, k, -1>(p)) g[k] += box_wall_term<Q, k, -1, ST, S::opp(k)>(F, p);
+        });
+    }
+    collide<Q, MODEL, ST::shifted>(g, rp);
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        const R wv = p.top ? lid_value<ST, S::opp(k)>(F) : R(0);  // a wall lane's term in slot kbar
+        o.st(i, S::opp(k), p.fluid ? g[k] : wv);
+    });
+}
+
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND, int PART>
 __device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
 {
@@ -639,7 +795,8 @@ __device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>
     else if constexpr (KIND == KIND_AA_ODD) cell_aa_odd<Q, MODEL, ST, LAYOUT, PART, false>(F, p, i);
     else if constexpr (KIND == KIND_AA_ODD_Z) cell_aa_odd<Q, MODEL, ST, LAYOUT, PART, true>(F, p, i);
     else if constexpr (KIND == KIND_PULL) cell_pull<Q, MODEL, ST, LAYOUT, PART, false>(F, p, i);
-    else cell_pull<Q, MODEL, ST, LAYOUT, PART, true>(F, p, i);
+    else if constexpr (KIND == KIND_PULL_Z) cell_pull<Q, MODEL, ST, LAYOUT, PART, true>(F, p, i);
+    else box_pull_cell<Q, MODEL, ST, LAYOUT>(F, p, i);
 }
 
 // Block b of nb fast-part blocks in the order the cells are visited.
@@ -756,7 +913,7 @@ __device__ __forceinline__ void group_step(const Field& F, const Relax<real_t<ST
             R g[Q];
             static_for<0, Q>([&](auto K) { g[K] = R(v[K][c]); });
             collide<Q, MODEL, ST::shifted>(g, p);
-            static_for<0, Q>([&](auto K) { w[K][c] = T(g[K]); });
+            static_for<0, Q>([&](auto K) { w[K][c] = to_storage<ST>(g[K]); });
         });
         if (!fast) return;
         static_for<0, Q>([&](auto K) {
@@ -797,84 +954,6 @@ __global__ void __launch_bounds__(256) k_step_slow(Field F, RelaxD pd, const uin
     const uint32_t i = list[F.reverse ? n - 1 - j : j];
     if (i >= F.ntot) return;
     cell_step<Q, MODEL, ST, LAYOUT, KIND, PART_SLOW>(F, relax_of<real_t<ST>>(pd), i);
-}
-
-// ---------------------------------------------------------------------------
-// Box cavities of the built-in geometry, with every decision taken from the
-// cell's position instead of its flag byte: a cell is fluid iff
-// 1 <= x <= nx-2 (and so for y, z), its neighbour x +- c_k is a wall iff it
-// leaves that range, and a wall cell is a lid cell iff it lies in the layer
-// z = nz-1. Each direction then costs one load and one store whose address
-// is chosen per lane (neighbour slot, or the cell's own slot across a wall)
-// and the wall terms come from the lid table, so walls, faces, edges and
-// corners all stay on one branch-free path, with no flag traffic and no
-// second gather round. Used by the ensemble, whose members are such
-// cavities; ntot < 2^24 (exact float quotients below).
-
-// Lid term w_J of the table in the storage type.
-template <class ST, int J>
-__device__ __forceinline__ real_t<ST> lid_value(const Field& F)
-{
-    if constexpr (sizeof(typename ST::T) == 8) return F.lid.d[J];
-    else return F.lid.f[J];
-}
-
-struct BoxPos {
-    // lo[a]: coordinate a is 1; hi[a]: it is n_a - 2 (both for n_a = 3);
-    // top: the cell lies in the lid layer z = nz - 1.
-    bool fluid, top, lo[3], hi[3];
-};
-
-// floor(n / d) for n < 2^24 and d >= 1: the float quotient is within one of
-// the true one, and one correction step fixes it.
-__device__ __forceinline__ uint32_t udiv24(uint32_t n, uint32_t d, float rcp)
-{
-    uint32_t q = (uint32_t)((float)n * rcp);
-    const int32_t r = (int32_t)(n - q * d);
-    if (r < 0) --q;
-    else if (r >= (int32_t)d) ++q;
-    return q;
-}
-
-__device__ __forceinline__ BoxPos box_pos(const Field& F, uint32_t i, float rcp_nz, float rcp_ny)
-{
-    const uint32_t row = udiv24(i, (uint32_t)F.nz, rcp_nz);
-    const int z = (int)(i - row * (uint32_t)F.nz);
-    const uint32_t x = udiv24(row, (uint32_t)F.ny, rcp_ny);
-    const int y = (int)(row - x * (uint32_t)F.ny);
-    const int c[3] = {(int)x, y, z}, n[3] = {F.nx, F.ny, F.nz};
-    BoxPos p;
-    p.fluid = true;
-    for (int a = 0; a < 3; ++a) {
-        p.fluid = p.fluid && c[a] >= 1 && c[a] <= n[a] - 2;
-        p.lo[a] = c[a] == 1;
-        p.hi[a] = c[a] == n[a] - 2;
-    }
-    p.top = z == F.nz - 1;
-    return p;
-}
-
-// Fluid cell: x + s*c_k is a wall.
-template <int Q, int K, int SIGN>
-__device__ __forceinline__ bool box_wall(const BoxPos& p)
-{
-    bool w = false;
-    static_for<0, 3>([&](auto A) {
-        constexpr int a = A;
-        constexpr int c = SIGN * L<Q>::c(K, a);
-        if constexpr (c > 0) w = w || p.hi[a];
-        else if constexpr (c < 0) w = w || p.lo[a];
-    });
-    return w;
-}
-
-// Fluid cell whose neighbour x + s*c_k is a wall: the stored term of that
-// wall cell in slot J, a lid term iff the wall lies in the layer z = nz - 1.
-template <int Q, int K, int SIGN, class ST, int J>
-__device__ __forceinline__ real_t<ST> box_wall_term(const Field& F, const BoxPos& p)
-{
-    if constexpr (SIGN * L<Q>::cz(K) > 0) return p.hi[2] ? lid_value<ST, J>(F) : real_t<ST>(0);
-    else return real_t<ST>(0);
 }
 
 // One step of one cell of a box cavity. AA even: local collide, slot kbar.
@@ -927,9 +1006,9 @@ __device__ __forceinline__ void box_cell(const Field& F, const Relax<real_t<ST>>
         constexpr int k = K;
         const R wv = p.top ? lid_value<ST, S::opp(k)>(F) : R(0);  // a wall lane's term in slot kbar
         if constexpr (KIND == KIND_AA_EVEN || KIND == KIND_PULL) {
-            *at(dst, S::opp(k) * sb + ib) = T(p.fluid ? g[k] : wv);
+            *at(dst, S::opp(k) * sb + ib) = to_storage<ST>(p.fluid ? g[k] : wv);
         } else if constexpr (k == S::rest) {
-            *at(dst, k * sb + ib) = T(p.fluid ? g[k] : wv);
+            *at(dst, k * sb + ib) = to_storage<ST>(p.fluid ? g[k] : wv);
         } else {
             // Fluid: pop_k(x + c_k) <- f_out_k, or pop_kbar(x) <- f_out_k +
             // w_k(x + c_k) across a wall. Wall lane: its own slot kbar.
@@ -937,7 +1016,7 @@ __device__ __forceinline__ void box_cell(const Field& F, const Relax<real_t<ST>>
             const uint32_t nb = k * sb + ib + (uint32_t)(offset<Q, k, 1>(F) * (int32_t)sz);
             const uint32_t off = p.fluid && !w ? nb : S::opp(k) * sb + ib;
             const R v = !p.fluid ? wv : (w ? g[k] + box_wall_term<Q, k, 1, ST, k>(F, p) : g[k]);
-            *at(dst, off) = T(v);
+            *at(dst, off) = to_storage<ST>(v);
         }
     });
 }

@@ -458,6 +458,8 @@ struct lbm_handle {
     uint32_t lds_local = 0;         //   kernels of local kinds
     uint32_t lds_neighbour = 0;     //   and of the kinds that reach neighbours
     bool custom_walls = false;      // wall terms set per cell (lbm_set_geometry)
+    int pull_kernel = 0;            // LBM_PULL_KERNEL: 0 by measurement, 1 flag-driven ("flag"),
+                                    //   2 position-driven on the built-in cavity ("box")
     double* qlink = nullptr;        // curved-wall distances q[k][ntot] (lbm_set_wall_distances)
     bool reverse_blocks = false;    // LBM_REVERSE_BLOCKS: step kernels visit cells in reverse order
     bool use_graph = false;         // small lattice: replay captured steps
@@ -483,6 +485,7 @@ struct lbm_handle {
         F.qlink = qlink;
         F.lid = lid_terms(q, (int)elem_bytes(d.storage_dtype), d.lid_velocity);
         F.zrecip = reciprocal64(d.nz);
+        F.yrecip = reciprocal64(d.ny);
         return F;
     }
     Launch base(int op) const
@@ -605,8 +608,10 @@ static int init_state(lbm_handle* h, const double* rho, const double* u)
 // the kinds that reach neighbours, the slow part over the listed cells.
 static uint32_t step_lds(const lbm_handle* h, int kind)
 {
-    if (h->lds_override) return kind == KIND_AA_ODD || kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_PULL
-                                    ? h->lds_neighbour : h->lds_local;
+    if (h->lds_override)
+        return kind == KIND_AA_ODD || kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_PULL ||
+                       kind == KIND_PULL_BOX
+                   ? h->lds_neighbour : h->lds_local;
     return residency_lds(step_waves((int)elem_bytes(h->d.storage_dtype), kind), h->block);
 }
 
@@ -614,8 +619,26 @@ static uint32_t step_lds(const lbm_handle* h, int kind)
 // lattices with z-wrap cells, whose edge list then leaves those cells out.
 static bool zwrap_kind(int kind) { return kind == KIND_PULL || kind == KIND_AA_ODD; }
 
+// The built-in cavity (no caller walls, no curved links) takes the pull kind
+// whose decisions come from the cell's position, with no edge part, where it
+// measured faster than the flag-driven one (256^3 cavity, MLUPS): FP32 and
+// FP16 in the blocked layout (34.6 k -> 36.9 k, 67.2 k -> 76.4 k) and FP32 in
+// SoA (33.8 k -> 35.6 k). FP64 keeps the flag-driven kernel (blocked 18.1 k
+// against 17.9-18.2 k at its best residency; SoA 16.8 k against 14.0 k),
+// and so does FP16 in SoA (61.7 k against 53.8 k): where the loads are the
+// limit, the work before them (the position, an address per lane and
+// direction) costs more than the second round of loads it saves.
+static bool box_pull(const lbm_handle* h, int kind)
+{
+    const size_t s = elem_bytes(h->d.storage_dtype);
+    const bool faster = (h->d.layout == LBM_BLOCKED && s < 8) || (h->d.layout == LBM_SOA && s == 4);
+    return kind == KIND_PULL && (h->pull_kernel == 2 || (h->pull_kernel == 0 && faster)) &&
+           h->d.geometry == LBM_CAVITY && !h->custom_walls && !h->qlink && h->cpt == 1;
+}
+
 static int fast_kind(const lbm_handle* h, int kind)
 {
+    if (box_pull(h, kind)) return KIND_PULL_BOX;
     if (!zwrap_kind(kind) || h->n_slow_z == h->n_slow) return kind;
     return kind == KIND_PULL ? KIND_PULL_Z : KIND_AA_ODD_Z;
 }
@@ -634,7 +657,8 @@ static int run_kind(lbm_handle* h, int kind)
     const uint32_t n_slow = zwrap_kind(kind) ? h->n_slow_z : h->n_slow;
     if (cpt == 1) {  // one launch, the edge part in the leading blocks
         L.kind = fast_kind(h, kind);
-        if (neighbours && n_slow > 0) {
+        L.lds = step_lds(h, L.kind);
+        if (neighbours && n_slow > 0 && L.kind != KIND_PULL_BOX) {
             L.slow_list = zwrap_kind(kind) ? h->slow_list_z : h->slow_list;
             L.n_slow = n_slow;
             L.edge_blocks = grid_for(n_slow, L.block);
@@ -673,7 +697,7 @@ static int run_kind_overlapped(lbm_handle* h, int kind)
 {
     const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD || kind == KIND_PULL;
     const uint32_t n_slow = zwrap_kind(kind) ? h->n_slow_z : h->n_slow;
-    if (!h->aux || n_slow == 0 || !(neighbours || h->cpt > 1)) return run_kind(h, kind);
+    if (!h->aux || n_slow == 0 || !(neighbours || h->cpt > 1) || box_pull(h, kind)) return run_kind(h, kind);
     HIP_TRY(hipEventRecord(h->fork, h->stream), "hipEventRecord");
     HIP_TRY(hipStreamWaitEvent(h->aux, h->fork, 0), "hipStreamWaitEvent");
     Launch S = h->base(OP_STEP_SLOW);
@@ -1031,6 +1055,8 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
     if (int rc = build_tables(h)) return bail(rc, lbm_last_error());
     h->use_graph = h->ntot <= kGraphCells && !std::getenv("LBM_NO_GRAPH");
     h->reverse_blocks = std::getenv("LBM_REVERSE_BLOCKS") != nullptr;
+    if (const char* e = std::getenv("LBM_PULL_KERNEL"))
+        h->pull_kernel = std::strcmp(e, "flag") == 0 ? 1 : (std::strcmp(e, "box") == 0 ? 2 : 0);
     if (std::getenv("LBM_NO_RESIDENCY_CAP")) h->lds_override = true;  // lds_local = lds_neighbour = 0
     if (const char* e = std::getenv("LBM_STEP_LDS")) {  // "bytes" or "local,neighbour"
         unsigned a = 0, b = 0;

@@ -1,0 +1,111 @@
+"""The position-driven 2Pop pull kernel of the built-in cavity (every wall,
+edge and corner decision taken from the cell's coordinates, no flag byte and
+no edge-cell list) against the FP64 oracle, and bit for bit against the
+flag-driven pull kernel in every storage type and layout.
+
+LBM_PULL_KERNEL picks the kernel when a lattice is created: "box" forces the
+position-driven one on the built-in cavity, "flag" the flag-driven one;
+unset, the library takes whichever measured faster for the storage type and
+layout."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2010_11751_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def lbm(hiplib):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return hiplib
+
+
+def lattice(lbm, monkeypatch, kernel, *args, **kw):
+    monkeypatch.setenv("LBM_PULL_KERNEL", kernel)
+    try:
+        return lbm.Lattice(*args, **kw)
+    finally:
+        monkeypatch.delenv("LBM_PULL_KERNEL")
+
+
+@pytest.mark.parametrize("layout", ("soa", "aos", "blocked"))
+@pytest.mark.parametrize("q,coll", [(19, "bgk"), (19, "trt"), (19, "cm"), (27, "rr"), (27, "bgk")])
+def test_box_pull_fp64_matches_oracle(lbm, monkeypatch, q, coll, layout):
+    """Ragged cavities (rows shorter and longer than a wave) with a lid moving
+    in all three directions: eager steps, then graph replays."""
+    for nx, ny, nz in ((12, 10, 14), (5, 7, 70)):
+        omega = 1.73
+        lid = (0.04, -0.015, 0.01)
+        print(f"case: box pull q={q} {coll} {layout} {nx}x{ny}x{nz}", flush=True)
+        sim = lattice(lbm, monkeypatch, "box", q, nx, ny, nz, scheme="2pop_pull", collision=coll, omega=omega,
+                      layout=layout, lid_velocity=lid)
+        ref = O.Simulation(O.Config(q=q, nx=nx, ny=ny, nz=nz, model=O.MODELS[coll], omega=omega, u_lid=lid),
+                           "ref")
+        for n in (1, 6, 70):
+            sim.step(n)
+            ref.step(n)
+            assert np.abs(sim.populations().cpu().numpy() - ref.populations()).max() <= TOL, n
+        m, _ = sim.invariants()
+        rm, _ = ref.invariants()
+        assert abs(m - rm) <= 1e-12 * rm
+
+
+@pytest.mark.parametrize("dtype", ("f64", "f32", "f16"))
+@pytest.mark.parametrize("layout", ("soa", "blocked"))
+@pytest.mark.parametrize("q,coll", [(19, "trt"), (27, "rr")])
+def test_box_pull_equals_flag_pull(lbm, monkeypatch, q, coll, layout, dtype):
+    """Same bits as the flag-driven kernel, shifted storage included (the
+    wall terms come from the same table rounded to the storage type)."""
+    nx, ny, nz = 13, 11, 66
+    kw = dict(scheme="2pop_pull", collision=coll, omega=1.91, layout=layout, dtype=dtype,
+              lid_velocity=(0.05, 0.01, 0.0))
+    got = {}
+    for kernel in ("box", "flag"):
+        sim = lattice(lbm, monkeypatch, kernel, q, nx, ny, nz, **kw)
+        sim.step(37)
+        got[kernel] = sim.populations().cpu()
+        sim.step(64)
+        got[kernel + "_later"] = sim.populations().cpu()
+    assert torch.equal(got["box"], got["flag"])
+    assert torch.equal(got["box_later"], got["flag_later"])
+
+
+def test_box_pull_default_choice_at_256(lbm, monkeypatch):
+    """The benchmark's FP32 blocked cavity: the default kernel (position-driven
+    for this storage and layout) equals the flag-driven one after a few steps."""
+    cav = W.CAVITY_256
+    got = []
+    for kernel in ("", "flag"):
+        print(f"case: 256^3 f32 blocked pull, kernel '{kernel or 'default'}'", flush=True)
+        sim = lattice(lbm, monkeypatch, kernel, 19, cav.n, scheme="2pop_pull", collision="bgk", omega=cav.omega,
+                      u_lid=cav.u_lid, dtype="f32", layout="blocked")
+        sim.step(5)
+        got.append(sim.populations().cpu())
+        del sim
+        torch.cuda.empty_cache()
+    assert torch.equal(got[0], got[1])
+
+
+def test_caller_walls_leave_the_box_kernel(lbm, monkeypatch):
+    """After lbm_set_geometry the wall terms are per cell, so the flag-driven
+    kernel takes over: a moving obstacle changes the flow as in the oracle."""
+    nx, ny, nz, omega = 10, 9, 12, 1.6
+    sim = lattice(lbm, monkeypatch, "box", 19, nx, ny, nz, scheme="2pop_pull", collision="bgk", omega=omega,
+                  u_lid=0.03)
+    cfg = O.Config(q=19, nx=nx, ny=ny, nz=nz, omega=omega, u_lid=(0.03, 0.0, 0.0))
+    types = O.flags(cfg).copy()
+    wu = np.zeros((3, cfg.ntot))
+    wu[0, types == O.LID] = 0.03
+    c = ((nx // 2) * ny + ny // 2) * nz + nz // 2
+    types[c] = O.WALL
+    wu[1, c] = 0.02
+    sim.set_geometry(torch.from_numpy(types), torch.from_numpy(wu), None)
+    ref = O.Simulation(cfg, "ref", cell_types=types, wall_u=wu)
+    sim.step(9)
+    ref.step(9)
+    assert np.abs(sim.populations().cpu().numpy() - ref.populations()).max() <= TOL
