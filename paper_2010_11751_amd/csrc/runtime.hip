@@ -621,17 +621,18 @@ static bool zwrap_kind(int kind) { return kind == KIND_PULL || kind == KIND_AA_O
 
 // The built-in cavity (no caller walls, no curved links) takes the pull kind
 // whose decisions come from the cell's position, with no edge part, where it
-// measured faster than the flag-driven one (256^3 cavity, MLUPS): FP32 and
-// FP16 in the blocked layout (34.6 k -> 36.9 k, 67.2 k -> 76.4 k) and FP32 in
-// SoA (33.8 k -> 35.6 k). FP64 keeps the flag-driven kernel (blocked 18.1 k
-// against 17.9-18.2 k at its best residency; SoA 16.8 k against 14.0 k),
-// and so does FP16 in SoA (61.7 k against 53.8 k): where the loads are the
-// limit, the work before them (the position, an address per lane and
-// direction) costs more than the second round of loads it saves.
+// measured faster than the flag-driven one (D3Q19 256^3 cavity, MLUPS): FP32
+// and FP16 in the blocked layout (34.6 k -> 36.9 k, 67.2 k -> 76.4 k) and
+// FP32 in SoA (33.8 k -> 35.6 k). FP64 keeps the flag-driven kernel (blocked
+// 18.1 k against 17.9-18.2 k at its best residency; SoA 16.8 k against
+// 14.0 k), and so do FP16 in SoA (61.7 k against 53.8 k) and D3Q27 (FP32 SoA
+// 512^3: 23.9 k against 12.1 k): where the loads are the limit, the work
+// before them (the position, an address per lane and direction) costs more
+// than the second round of loads it saves.
 static bool box_pull(const lbm_handle* h, int kind)
 {
     const size_t s = elem_bytes(h->d.storage_dtype);
-    const bool faster = (h->d.layout == LBM_BLOCKED && s < 8) || (h->d.layout == LBM_SOA && s == 4);
+    const bool faster = h->q == 19 && ((h->d.layout == LBM_BLOCKED && s < 8) || (h->d.layout == LBM_SOA && s == 4));
     return kind == KIND_PULL && (h->pull_kernel == 2 || (h->pull_kernel == 0 && faster)) &&
            h->d.geometry == LBM_CAVITY && !h->custom_walls && !h->qlink && h->cpt == 1;
 }
