@@ -38,6 +38,9 @@ hipError_t launch_step_kind(const Launch& L, hipStream_t s)
     case KIND_PULL_Z: k_step<Q, MODEL, ST, LAYOUT, KIND_PULL_Z><<<g, b, lds, s>>>(L.F, L.relax, el, ne, eb); break;
     case KIND_AA_ODD_Z: k_step<Q, MODEL, ST, LAYOUT, KIND_AA_ODD_Z><<<g, b, lds, s>>>(L.F, L.relax, el, ne, eb); break;
     case KIND_PULL_BOX: k_step<Q, MODEL, ST, LAYOUT, KIND_PULL_BOX><<<g, b, lds, s>>>(L.F, L.relax, nullptr, 0, 0); break;
+    case KIND_AA_ODD_BOX:
+        k_step<Q, MODEL, ST, LAYOUT, KIND_AA_ODD_BOX><<<g, b, lds, s>>>(L.F, L.relax, nullptr, 0, 0);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -741,23 +741,28 @@ __device__ __forceinline__ real_t<ST> box_wall_term(const Field& F, const BoxPos
     else return real_t<ST>(0);
 }
 
-// Pull kind for the built-in cavity of a single lattice (either layout),
-// every decision taken from the cell's position as in the box kernels below:
-// a fluid lane gathers pop_kbar(x - c_k), or its own pop_k(x) plus the wall's
-// term from the lid table across a wall, with one load per direction at an
-// address chosen per lane; wall lanes load nothing and write their terms into
-// the other array. No flag byte, no second round of loads for cells next to
-// a wall, and no edge-cell list (edges and corners take the same path). The
-// sums are those of the flag-driven pull kernel, operand for operand.
-template <int Q, int MODEL, class ST, int LAYOUT>
-__device__ __forceinline__ void box_pull_cell(const Field& F, const Relax<real_t<ST>>& rp, uint32_t i)
+// Pull and AA odd kinds for the built-in cavity of a single lattice (any
+// layout), every decision taken from the cell's position as in the box
+// kernels below. A fluid lane gathers pop_kbar(x - c_k), or its own pop_k(x)
+// plus the wall's term from the lid table across a wall, with one load per
+// direction at an address chosen per lane. Pull: store out_kbar(x); wall
+// lanes load nothing and write their terms into the other array. AA odd:
+// store pop_k(x + c_k), or pop_kbar(x) <- f_out_k + w_k(x + c_k) across a
+// wall; wall lanes do nothing. No flag byte, no second round of loads for
+// cells next to a wall, and no edge-cell list (edges and corners take the
+// same path). The sums are those of the flag-driven kernels, operand for
+// operand.
+template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
+__device__ __forceinline__ void box_step_cell(const Field& F, const Relax<real_t<ST>>& rp, uint32_t i)
 {
     using S = L<Q>;
     using R = real_t<ST>;
     using T = typename ST::T;
+    constexpr bool pull = KIND == KIND_PULL_BOX;
     const Acc<ST, LAYOUT, Q, true> a{(T*)F.pop, F.stride};
-    const Acc<ST, LAYOUT, Q, true> o{(T*)F.out, F.stride};
+    const Acc<ST, LAYOUT, Q, true> o{(T*)(pull ? F.out : F.pop), F.stride};
     const BoxPos p = box_pos64(F, i);
+    if (!pull && !p.fluid) return;
     R g[Q];
     static_for<0, Q>([&](auto K) { g[K] = R(0); });
     if (p.fluid) {
@@ -780,8 +785,16 @@ __device__ __forceinline__ void box_pull_cell(const Field& F, const Relax<real_t
     collide<Q, MODEL, ST::shifted>(g, rp);
     static_for<0, Q>([&](auto K) {
         constexpr int k = K;
-        const R wv = p.top ? lid_value<ST, S::opp(k)>(F) : R(0);  // a wall lane's term in slot kbar
-        o.st(i, S::opp(k), p.fluid ? g[k] : wv);
+        if constexpr (pull) {
+            const R wv = p.top ? lid_value<ST, S::opp(k)>(F) : R(0);  // a wall lane's term in slot kbar
+            o.st(i, S::opp(k), p.fluid ? g[k] : wv);
+        } else if constexpr (k == S::rest) {
+            o.st(i, k, g[k]);
+        } else {
+            const bool w = box_wall<Q, k, 1>(p);
+            T* const dst = w ? o.ptr(i, S::opp(k)) : o.ptr_shift(i, k, offset<Q, k, 1>(F));
+            *dst = to_storage<ST>(w ? g[k] + box_wall_term<Q, k, 1, ST, k>(F, p) : g[k]);
+        }
     });
 }
 
@@ -796,7 +809,7 @@ __device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>
     else if constexpr (KIND == KIND_AA_ODD_Z) cell_aa_odd<Q, MODEL, ST, LAYOUT, PART, true>(F, p, i);
     else if constexpr (KIND == KIND_PULL) cell_pull<Q, MODEL, ST, LAYOUT, PART, false>(F, p, i);
     else if constexpr (KIND == KIND_PULL_Z) cell_pull<Q, MODEL, ST, LAYOUT, PART, true>(F, p, i);
-    else box_pull_cell<Q, MODEL, ST, LAYOUT>(F, p, i);
+    else box_step_cell<Q, MODEL, ST, LAYOUT, KIND>(F, p, i);
 }
 
 // Block b of nb fast-part blocks in the order the cells are visited.

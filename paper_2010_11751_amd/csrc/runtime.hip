@@ -460,6 +460,7 @@ struct lbm_handle {
     bool custom_walls = false;      // wall terms set per cell (lbm_set_geometry)
     int pull_kernel = 0;            // LBM_PULL_KERNEL: 0 by measurement, 1 flag-driven ("flag"),
                                     //   2 position-driven on the built-in cavity ("box")
+    int aa_kernel = 0;              // LBM_AA_KERNEL, the same for the AA odd kind
     double* qlink = nullptr;        // curved-wall distances q[k][ntot] (lbm_set_wall_distances)
     bool reverse_blocks = false;    // LBM_REVERSE_BLOCKS: step kernels visit cells in reverse order
     bool use_graph = false;         // small lattice: replay captured steps
@@ -610,7 +611,7 @@ static uint32_t step_lds(const lbm_handle* h, int kind)
 {
     if (h->lds_override)
         return kind == KIND_AA_ODD || kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_PULL ||
-                       kind == KIND_PULL_BOX
+                       kind == KIND_PULL_BOX || kind == KIND_AA_ODD_BOX
                    ? h->lds_neighbour : h->lds_local;
     return residency_lds(step_waves((int)elem_bytes(h->d.storage_dtype), kind), h->block);
 }
@@ -619,27 +620,45 @@ static uint32_t step_lds(const lbm_handle* h, int kind)
 // lattices with z-wrap cells, whose edge list then leaves those cells out.
 static bool zwrap_kind(int kind) { return kind == KIND_PULL || kind == KIND_AA_ODD; }
 
-// The built-in cavity (no caller walls, no curved links) takes the pull kind
-// whose decisions come from the cell's position, with no edge part, where it
-// measured faster than the flag-driven one (D3Q19 256^3 cavity, MLUPS): FP32
-// and FP16 in the blocked layout (34.6 k -> 36.9 k, 67.2 k -> 76.4 k) and
-// FP32 in SoA (33.8 k -> 35.6 k). FP64 keeps the flag-driven kernel (blocked
-// 18.1 k against 17.9-18.2 k at its best residency; SoA 16.8 k against
-// 14.0 k), and so do FP16 in SoA (61.7 k against 53.8 k) and D3Q27 (FP32 SoA
-// 512^3: 23.9 k against 12.1 k): where the loads are the limit, the work
-// before them (the position, an address per lane and direction) costs more
-// than the second round of loads it saves.
-static bool box_pull(const lbm_handle* h, int kind)
+// On the built-in cavity (no caller walls, no curved links) the pull and AA
+// odd kinds have position-driven forms with no edge part. The library takes
+// them where they measured faster than the flag-driven ones (MLUPS,
+// flag-driven -> position-driven):
+//   2Pop pull, D3Q19 256^3: FP32 blocked 34.6 k -> 36.9 k, SoA 33.8 k ->
+//     35.6 k; FP16 blocked 67.2 k -> 76.4 k. Slower: FP64 (blocked 18.1 k ->
+//     17.6-18.2 k, SoA 16.8 k -> 14.0 k) and FP16 SoA (61.7 k -> 53.8 k).
+//   2Pop pull, D3Q27 RR 320^3: blocked FP32 23.5 k -> 25.0 k, FP16 46.7 k ->
+//     50.2 k. Slower in SoA (FP32 23.5 k -> 12.0 k, FP16 40.7 k -> 14.7 k).
+//   AA, D3Q19 256^3: SoA FP64 16.6 k -> 16.8 k, FP32 33.5 k -> 34.5 k, FP16
+//     55.8 k -> 66.3 k; blocked FP64 15.3 k -> 17.1 k, FP32 32.5 k -> 34.3 k,
+//     FP16 58.1 k -> 69.1 k.
+//   AA, D3Q27 RR 320^3: SoA FP32 20.8 k -> 23.4 k, FP16 32.0 k -> 42.3 k;
+//     blocked FP32 20.0 k -> 23.6 k, FP16 34.8 k -> 46.4 k.
+// Where the loads are the limit, the work before them (the position, an
+// address chosen per lane and direction) can cost more than the second
+// round of loads for cells next to a wall, the flag byte and the loads of
+// wall lanes that it saves. LBM_PULL_KERNEL and LBM_AA_KERNEL ("box" or
+// "flag") override the choice.
+static bool box_measured_faster(const lbm_handle* h, int kind)
 {
     const size_t s = elem_bytes(h->d.storage_dtype);
-    const bool faster = h->q == 19 && ((h->d.layout == LBM_BLOCKED && s < 8) || (h->d.layout == LBM_SOA && s == 4));
-    return kind == KIND_PULL && (h->pull_kernel == 2 || (h->pull_kernel == 0 && faster)) &&
-           h->d.geometry == LBM_CAVITY && !h->custom_walls && !h->qlink && h->cpt == 1;
+    const bool soa = h->d.layout == LBM_SOA, blocked = h->d.layout == LBM_BLOCKED;
+    if (kind == KIND_AA_ODD) return (soa || blocked) && (h->q == 19 || s < 8);
+    if (kind == KIND_PULL) return h->q == 19 ? ((blocked && s < 8) || (soa && s == 4)) : (blocked && s < 8);
+    return false;
+}
+
+static bool box_kind(const lbm_handle* h, int kind)
+{
+    if (kind != KIND_PULL && kind != KIND_AA_ODD) return false;
+    const int choice = kind == KIND_PULL ? h->pull_kernel : h->aa_kernel;
+    return (choice == 2 || (choice == 0 && box_measured_faster(h, kind))) && h->d.geometry == LBM_CAVITY &&
+           !h->custom_walls && !h->qlink && h->cpt == 1;
 }
 
 static int fast_kind(const lbm_handle* h, int kind)
 {
-    if (box_pull(h, kind)) return KIND_PULL_BOX;
+    if (box_kind(h, kind)) return kind == KIND_PULL ? KIND_PULL_BOX : KIND_AA_ODD_BOX;
     if (!zwrap_kind(kind) || h->n_slow_z == h->n_slow) return kind;
     return kind == KIND_PULL ? KIND_PULL_Z : KIND_AA_ODD_Z;
 }
@@ -659,7 +678,7 @@ static int run_kind(lbm_handle* h, int kind)
     if (cpt == 1) {  // one launch, the edge part in the leading blocks
         L.kind = fast_kind(h, kind);
         L.lds = step_lds(h, L.kind);
-        if (neighbours && n_slow > 0 && L.kind != KIND_PULL_BOX) {
+        if (neighbours && n_slow > 0 && L.kind != KIND_PULL_BOX && L.kind != KIND_AA_ODD_BOX) {
             L.slow_list = zwrap_kind(kind) ? h->slow_list_z : h->slow_list;
             L.n_slow = n_slow;
             L.edge_blocks = grid_for(n_slow, L.block);
@@ -698,7 +717,7 @@ static int run_kind_overlapped(lbm_handle* h, int kind)
 {
     const bool neighbours = kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_AA_ODD || kind == KIND_PULL;
     const uint32_t n_slow = zwrap_kind(kind) ? h->n_slow_z : h->n_slow;
-    if (!h->aux || n_slow == 0 || !(neighbours || h->cpt > 1) || box_pull(h, kind)) return run_kind(h, kind);
+    if (!h->aux || n_slow == 0 || !(neighbours || h->cpt > 1) || box_kind(h, kind)) return run_kind(h, kind);
     HIP_TRY(hipEventRecord(h->fork, h->stream), "hipEventRecord");
     HIP_TRY(hipStreamWaitEvent(h->aux, h->fork, 0), "hipStreamWaitEvent");
     Launch S = h->base(OP_STEP_SLOW);
@@ -1058,6 +1077,8 @@ lbm_handle* lbm_create_ex(const lbm_desc* d)
     h->reverse_blocks = std::getenv("LBM_REVERSE_BLOCKS") != nullptr;
     if (const char* e = std::getenv("LBM_PULL_KERNEL"))
         h->pull_kernel = std::strcmp(e, "flag") == 0 ? 1 : (std::strcmp(e, "box") == 0 ? 2 : 0);
+    if (const char* e = std::getenv("LBM_AA_KERNEL"))
+        h->aa_kernel = std::strcmp(e, "flag") == 0 ? 1 : (std::strcmp(e, "box") == 0 ? 2 : 0);
     if (std::getenv("LBM_NO_RESIDENCY_CAP")) h->lds_override = true;  // lds_local = lds_neighbour = 0
     if (const char* e = std::getenv("LBM_STEP_LDS")) {  // "bytes" or "local,neighbour"
         unsigned a = 0, b = 0;

@@ -1,12 +1,12 @@
-"""The position-driven 2Pop pull kernel of the built-in cavity (every wall,
-edge and corner decision taken from the cell's coordinates, no flag byte and
-no edge-cell list) against the FP64 oracle, and bit for bit against the
-flag-driven pull kernel in every storage type and layout.
+"""The position-driven 2Pop pull and AA odd kernels of the built-in cavity
+(every wall, edge and corner decision taken from the cell's coordinates, no
+flag byte and no edge-cell list) against the FP64 oracle, and bit for bit
+against the flag-driven kernels in every storage type and layout.
 
-LBM_PULL_KERNEL picks the kernel when a lattice is created: "box" forces the
-position-driven one on the built-in cavity, "flag" the flag-driven one;
-unset, the library takes whichever measured faster for the storage type and
-layout."""
+LBM_PULL_KERNEL (LBM_AA_KERNEL for the AA odd step) picks the kernel when a
+lattice is created: "box" forces the position-driven one on the built-in
+cavity, "flag" the flag-driven one; unset, the library takes whichever
+measured faster for the storage type and layout."""
 import numpy as np
 import pytest
 import torch
@@ -26,11 +26,12 @@ def lbm(hiplib):
 
 
 def lattice(lbm, monkeypatch, kernel, *args, **kw):
-    monkeypatch.setenv("LBM_PULL_KERNEL", kernel)
+    var = "LBM_AA_KERNEL" if kw.get("scheme") == "aa" else "LBM_PULL_KERNEL"
+    monkeypatch.setenv(var, kernel)
     try:
         return lbm.Lattice(*args, **kw)
     finally:
-        monkeypatch.delenv("LBM_PULL_KERNEL")
+        monkeypatch.delenv(var)
 
 
 @pytest.mark.parametrize("layout", ("soa", "aos", "blocked"))
@@ -109,3 +110,35 @@ def test_caller_walls_leave_the_box_kernel(lbm, monkeypatch):
     sim.step(9)
     ref.step(9)
     assert np.abs(sim.populations().cpu().numpy() - ref.populations()).max() <= TOL
+
+
+@pytest.mark.parametrize("layout", ("soa", "aos", "blocked"))
+@pytest.mark.parametrize("q,coll", [(19, "bgk"), (19, "trt"), (27, "rr")])
+def test_box_aa_fp64_matches_oracle(lbm, monkeypatch, q, coll, layout):
+    """AA with the position-driven odd step: odd and even step counts, graph
+    replays, a lid moving in all three directions."""
+    nx, ny, nz, omega, lid = 12, 10, 14, 1.73, (0.04, -0.015, 0.01)
+    print(f"case: box aa q={q} {coll} {layout}", flush=True)
+    sim = lattice(lbm, monkeypatch, "box", q, nx, ny, nz, scheme="aa", collision=coll, omega=omega, layout=layout,
+                  lid_velocity=lid)
+    ref = O.Simulation(O.Config(q=q, nx=nx, ny=ny, nz=nz, model=O.MODELS[coll], omega=omega, u_lid=lid), "ref")
+    for n in (1, 6, 70, 3):
+        sim.step(n)
+        ref.step(n)
+        assert np.abs(sim.populations().cpu().numpy() - ref.populations()).max() <= TOL, n
+
+
+@pytest.mark.parametrize("dtype", ("f32", "f16"))
+@pytest.mark.parametrize("q,coll", [(19, "trt"), (27, "rr")])
+def test_box_aa_equals_flag_aa(lbm, monkeypatch, q, coll, dtype):
+    nx, ny, nz = 13, 11, 66
+    kw = dict(scheme="aa", collision=coll, omega=1.91, dtype=dtype, lid_velocity=(0.05, 0.01, 0.0))
+    got = {}
+    for kernel in ("box", "flag"):
+        sim = lattice(lbm, monkeypatch, kernel, q, nx, ny, nz, **kw)
+        sim.step(37)
+        got[kernel] = sim.populations().cpu()
+        sim.step(64)
+        got[kernel + "_later"] = sim.populations().cpu()
+    assert torch.equal(got["box"], got["flag"])
+    assert torch.equal(got["box_later"], got["flag_later"])
