@@ -41,6 +41,12 @@ hipError_t launch_step_kind(const Launch& L, hipStream_t s)
     case KIND_AA_ODD_BOX:
         k_step<Q, MODEL, ST, LAYOUT, KIND_AA_ODD_BOX><<<g, b, lds, s>>>(L.F, L.relax, nullptr, 0, 0);
         break;
+    case KIND_PULL_WRAP:
+        k_step<Q, MODEL, ST, LAYOUT, KIND_PULL_WRAP><<<g, b, lds, s>>>(L.F, L.relax, nullptr, 0, 0);
+        break;
+    case KIND_AA_ODD_WRAP:
+        k_step<Q, MODEL, ST, LAYOUT, KIND_AA_ODD_WRAP><<<g, b, lds, s>>>(L.F, L.relax, nullptr, 0, 0);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

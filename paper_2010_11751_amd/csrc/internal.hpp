@@ -40,7 +40,8 @@ constexpr uint32_t kBlockCells = LBM_BLOCK_CELLS;
 // for lattices with FL_ZWRAP cells.
 enum Kind {
     KIND_2POP = 0, KIND_SWAP_COLLIDE = 1, KIND_SWAP_STREAM = 2, KIND_AA_EVEN = 3, KIND_AA_ODD = 4, KIND_PULL = 5,
-    KIND_PULL_Z = 6, KIND_AA_ODD_Z = 7, KIND_PULL_BOX = 8, KIND_AA_ODD_BOX = 9
+    KIND_PULL_Z = 6, KIND_AA_ODD_Z = 7, KIND_PULL_BOX = 8, KIND_AA_ODD_BOX = 9, KIND_PULL_WRAP = 10,
+    KIND_AA_ODD_WRAP = 11
 };
 enum Storage { STORE_F64 = 0, STORE_F32 = 1, STORE_F16 = 2 };
 
@@ -123,7 +124,8 @@ constexpr int max_step_block(int q, int model, int elem_bytes)
 constexpr int min_step_waves(int q, int elem_bytes, int kind)
 {
     if (elem_bytes != 8) return 1;
-    return ((kind == 4 || kind == 5 || kind == 6 || kind == 7 || kind == 9) && q == 19) ? 3 : 2;
+    return ((kind == 4 || kind == 5 || kind == 6 || kind == 7 || kind == 9 || kind == 10 || kind == 11) && q == 19)
+               ? 3 : 2;
 }
 
 // Resident waves per SIMD the fast step kernels are held to (0: no limit),
@@ -141,7 +143,7 @@ constexpr int min_step_waves(int q, int elem_bytes, int kind)
 inline int step_waves(int elem_bytes, int kind)
 {
     if (kind == 8) return elem_bytes == 8 ? 2 : 0;
-    if (kind == 9) return elem_bytes == 8 ? 3 : 0;
+    if (kind == 9 || kind == 10 || kind == 11) return elem_bytes == 8 ? 3 : 0;
     if (elem_bytes == 8) return (kind == 4 || kind >= 5) ? 3 : 2;
     if (elem_bytes == 4) return (kind == 4 || kind == 2 || kind >= 5) ? 0 : 4;
     return 0;

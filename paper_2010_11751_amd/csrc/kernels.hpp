@@ -798,6 +798,73 @@ __device__ __forceinline__ void box_step_cell(const Field& F, const Relax<real_t
     });
 }
 
+// The same two kinds for the built-in periodic box (every cell fluid): the
+// neighbour index x +- c_k wraps on the faces by a per-lane correction taken
+// from the cell's position, so the z-face and the x / y-face cells need
+// neither the flag byte nor the edge-cell list. Gather f_k(x) from
+// pop_kbar(x - c_k); pull: store out_kbar(x); AA odd: store pop_k(x + c_k).
+struct WrapPos {
+    uint32_t lo[3], hi[3];  // N_a * span_a on the low / high face of axis a, else 0
+};
+
+__device__ __forceinline__ WrapPos wrap_pos(const Field& F, uint32_t i)
+{
+    // (a reciprocal of 0 stands for an axis of one cell)
+    const uint32_t row = F.zrecip ? (uint32_t)__umul64hi((unsigned long long)i, F.zrecip) : i;
+    const uint32_t z = i - row * (uint32_t)F.nz;
+    const uint32_t x = F.yrecip ? (uint32_t)__umul64hi((unsigned long long)row, F.yrecip) : row;
+    const uint32_t y = row - x * (uint32_t)F.ny;
+    const uint32_t plane = (uint32_t)F.ny * (uint32_t)F.nz;
+    WrapPos w;
+    w.lo[0] = x == 0 ? F.ntot : 0u;
+    w.hi[0] = x == (uint32_t)F.nx - 1 ? F.ntot : 0u;
+    w.lo[1] = y == 0 ? plane : 0u;
+    w.hi[1] = y == (uint32_t)F.ny - 1 ? plane : 0u;
+    w.lo[2] = z == 0 ? (uint32_t)F.nz : 0u;
+    w.hi[2] = z == (uint32_t)F.nz - 1 ? (uint32_t)F.nz : 0u;
+    return w;
+}
+
+// Index of x + SIGN c_K in the periodic box (32-bit arithmetic: the result
+// lies in [0, ntot)).
+template <int Q, int K, int SIGN>
+__device__ __forceinline__ uint32_t wrap_neighbour(const Field& F, uint32_t i, const WrapPos& w)
+{
+    uint32_t j = i + (uint32_t)offset<Q, K, SIGN>(F);
+    static_for<0, 3>([&](auto A) {
+        constexpr int a = A;
+        constexpr int c = SIGN * L<Q>::c(K, a);
+        if constexpr (c > 0) j -= w.hi[a];
+        else if constexpr (c < 0) j += w.lo[a];
+    });
+    return j;
+}
+
+template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
+__device__ __forceinline__ void wrap_step_cell(const Field& F, const Relax<real_t<ST>>& rp, uint32_t i)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    using T = typename ST::T;
+    constexpr bool pull = KIND == KIND_PULL_WRAP;
+    const Acc<ST, LAYOUT, Q, true> a{(T*)F.pop, F.stride};
+    const Acc<ST, LAYOUT, Q, true> o{(T*)(pull ? F.out : F.pop), F.stride};
+    const WrapPos w = wrap_pos(F, i);
+    R g[Q];
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k == S::rest) g[k] = a.ld(i, k);
+        else g[k] = a.ld(wrap_neighbour<Q, k, -1>(F, i, w), S::opp(k));
+    });
+    collide<Q, MODEL, ST::shifted>(g, rp);
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (pull) o.st(i, S::opp(k), g[k]);
+        else if constexpr (k == S::rest) o.st(i, k, g[k]);
+        else o.st(wrap_neighbour<Q, k, 1>(F, i, w), k, g[k]);
+    });
+}
+
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND, int PART>
 __device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>>& p, uint32_t i)
 {
@@ -809,7 +876,8 @@ __device__ __forceinline__ void cell_step(const Field& F, const Relax<real_t<ST>
     else if constexpr (KIND == KIND_AA_ODD_Z) cell_aa_odd<Q, MODEL, ST, LAYOUT, PART, true>(F, p, i);
     else if constexpr (KIND == KIND_PULL) cell_pull<Q, MODEL, ST, LAYOUT, PART, false>(F, p, i);
     else if constexpr (KIND == KIND_PULL_Z) cell_pull<Q, MODEL, ST, LAYOUT, PART, true>(F, p, i);
-    else box_step_cell<Q, MODEL, ST, LAYOUT, KIND>(F, p, i);
+    else if constexpr (KIND == KIND_PULL_BOX || KIND == KIND_AA_ODD_BOX) box_step_cell<Q, MODEL, ST, LAYOUT, KIND>(F, p, i);
+    else wrap_step_cell<Q, MODEL, ST, LAYOUT, KIND>(F, p, i);
 }
 
 // Block b of nb fast-part blocks in the order the cells are visited.
