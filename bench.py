@@ -34,13 +34,13 @@ KERNEL_LABEL = {"2pop_pull": "2Pop pull", "aa": "AA even/odd"}
 
 
 def kernel_label(r) -> str:
-    """The step kernel a headline run times (D3Q19). On the built-in cavity the
-    library takes the position-driven pull kernel for FP32 in either layout
-    and for FP16 in the blocked one, and the position-driven AA odd kernel in
-    SoA and the blocked layout (where they measured faster), the flag-driven
-    ones otherwise."""
+    """The step kernel a headline run times (D3Q19, 256^3). On the built-in
+    cavity the library takes the position-driven pull kernel except for FP64
+    in the blocked layout, and the position-driven AA odd kernel in SoA and
+    the blocked layout (where they measured faster), the flag-driven ones
+    otherwise."""
     label = KERNEL_LABEL[r["scheme"]]
-    if r["scheme"] == "2pop_pull" and (r["dtype"] == "f32" or (r["dtype"] == "f16" and r["layout"] == "blocked")):
+    if r["scheme"] == "2pop_pull" and not (r["dtype"] == "f64" and r["layout"] == "blocked"):
         label += ", position-driven"
     if r["scheme"] == "aa" and r["layout"] in ("soa", "blocked"):
         label += " (odd step position-driven)"

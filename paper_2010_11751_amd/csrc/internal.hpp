@@ -99,6 +99,7 @@ struct Field {
     LidTerms lid;          // terms of lid cells (built-in geometries)
     uint64_t zrecip;       // ceil(2^64 / nz) (nz >= 2; else 0): floor(i / nz) = high word of i * zrecip
     uint64_t yrecip;       // ceil(2^64 / ny), the same for the row index (x ny + y) -> x
+    int soa32;             // SoA whose streams and halo span under 4 GiB: 32-bit byte offsets suffice
 };
 
 // Largest block of the step kernels: the moment-space models (model >= 4)

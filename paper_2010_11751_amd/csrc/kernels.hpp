@@ -752,6 +752,61 @@ __device__ __forceinline__ real_t<ST> box_wall_term(const Field& F, const BoxPos
 // cells next to a wall, and no edge-cell list (edges and corners take the
 // same path). The sums are those of the flag-driven kernels, operand for
 // operand.
+// SoA arrays under 4 GiB (F.soa32): the same kinds with every address an
+// unsigned 32-bit byte offset from one base, the start of the halo before
+// stream 0. A lane's choice between its own slot and the neighbour's is then
+// one 32-bit select, and each load or store takes the common base in scalar
+// registers, where two 64-bit pointers into two streams cost a select each.
+template <int Q, int MODEL, class ST, int KIND>
+__device__ __forceinline__ void box_step_soa32(const Field& F, const Relax<real_t<ST>>& rp, uint32_t i,
+                                               const BoxPos& p)
+{
+    using S = L<Q>;
+    using R = real_t<ST>;
+    using T = typename ST::T;
+    constexpr bool pull = KIND == KIND_PULL_BOX;
+    constexpr uint32_t sz = sizeof(T);
+    const int64_t h = (int64_t)F.ny * F.nz + F.nz + 1;  // the largest neighbour offset
+    const char* const src = reinterpret_cast<const char*>(F.pop) - h * sz;
+    char* const dst = reinterpret_cast<char*>(pull ? F.out : F.pop) - h * sz;
+    const uint32_t lane = i * sz + (uint32_t)h * sz;
+    const uint32_t ssz = (uint32_t)F.stride * sz;  // bytes between streams (32-bit: the arrays fit)
+    auto off = [&](int k, int32_t d) -> uint32_t { return lane + (uint32_t)k * ssz + (uint32_t)(d * (int32_t)sz); };
+    // a if c else b, as arithmetic (a branch per direction otherwise)
+    auto pick = [](bool c, uint32_t a, uint32_t b) -> uint32_t { return b ^ ((a ^ b) & (0u - (uint32_t)c)); };
+    auto ld = [&](uint32_t o) -> R { return R(*reinterpret_cast<const T*>(src + o)); };
+    auto st = [&](uint32_t o, R v) { *reinterpret_cast<T*>(dst + o) = to_storage<ST>(v); };
+    if (!pull && !p.fluid) return;
+    R g[Q];
+    static_for<0, Q>([&](auto K) { g[K] = R(0); });
+    if (p.fluid) {
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            if constexpr (k == S::rest) g[k] = ld(off(k, 0));
+            else g[k] = ld(pick(box_wall<Q, k, -1>(p), off(k, 0), off(S::opp(k), offset<Q, k, -1>(F))));
+        });
+        static_for<0, Q>([&](auto K) {
+            constexpr int k = K;
+            if constexpr (k != S::rest)
+                if (box_wall<Q, k, -1>(p)) g[k] += box_wall_term<Q, k, -1, ST, S::opp(k)>(F, p);
+        });
+    }
+    collide<Q, MODEL, ST::shifted>(g, rp);
+    static_for<0, Q>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (pull) {
+            const R wv = p.top ? lid_value<ST, S::opp(k)>(F) : R(0);
+            st(off(S::opp(k), 0), p.fluid ? g[k] : wv);
+        } else if constexpr (k == S::rest) {
+            st(off(k, 0), g[k]);
+        } else {
+            const bool w = box_wall<Q, k, 1>(p);
+            st(pick(w, off(S::opp(k), 0), off(k, offset<Q, k, 1>(F))),
+               w ? g[k] + box_wall_term<Q, k, 1, ST, k>(F, p) : g[k]);
+        }
+    });
+}
+
 template <int Q, int MODEL, class ST, int LAYOUT, int KIND>
 __device__ __forceinline__ void box_step_cell(const Field& F, const Relax<real_t<ST>>& rp, uint32_t i)
 {
@@ -762,6 +817,12 @@ __device__ __forceinline__ void box_step_cell(const Field& F, const Relax<real_t
     const Acc<ST, LAYOUT, Q, true> a{(T*)F.pop, F.stride};
     const Acc<ST, LAYOUT, Q, true> o{(T*)(pull ? F.out : F.pop), F.stride};
     const BoxPos p = box_pos64(F, i);
+    if constexpr (LAYOUT == LAYOUT_SOA) {
+        if (F.soa32) {
+            box_step_soa32<Q, MODEL, ST, KIND>(F, rp, i, p);
+            return;
+        }
+    }
     if (!pull && !p.fluid) return;
     R g[Q];
     static_for<0, Q>([&](auto K) { g[K] = R(0); });

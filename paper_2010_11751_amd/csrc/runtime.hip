@@ -470,6 +470,15 @@ struct lbm_handle {
     int graph_phase = -1;           // AA phase and 2Pop buffer the graph starts from
     void* graph_pop = nullptr;
 
+    // SoA whose streams, with a neighbour offset's reach on either side, span
+    // under 4 GiB: the position-driven kernels then address it by 32-bit byte
+    // offsets from one base.
+    bool soa32() const
+    {
+        const uint64_t h = (uint64_t)d.ny * d.nz + d.nz + 1;
+        return d.layout == LBM_SOA &&
+               ((uint64_t)q * (uint64_t)stride + 2 * h) * elem_bytes(d.storage_dtype) < (1ull << 32);
+    }
     Field field() const
     {
         Field F;
@@ -487,6 +496,7 @@ struct lbm_handle {
         F.lid = lid_terms(q, (int)elem_bytes(d.storage_dtype), d.lid_velocity);
         F.zrecip = reciprocal64(d.nz);
         F.yrecip = reciprocal64(d.ny);
+        F.soa32 = soa32() ? 1 : 0;
         return F;
     }
     Launch base(int op) const
@@ -625,13 +635,16 @@ static bool zwrap_kind(int kind) { return kind == KIND_PULL || kind == KIND_AA_O
 // odd kinds have position-driven forms with no edge part. The library takes
 // them where they measured faster than the flag-driven ones (MLUPS,
 // flag-driven -> position-driven):
-//   2Pop pull, D3Q19 256^3: FP32 blocked 34.6 k -> 36.9 k, SoA 33.8 k ->
-//     35.6 k; FP16 blocked 67.2 k -> 76.4 k. Slower: FP64 (blocked 18.1 k ->
-//     17.6-18.2 k, SoA 16.8 k -> 14.0 k) and FP16 SoA (61.7 k -> 53.8 k).
+//   2Pop pull, D3Q19 256^3: FP32 blocked 34.6 k -> 36.9 k; FP16 blocked
+//     67.2 k -> 76.4 k; SoA with 32-bit offsets (arrays under 4 GiB) FP64
+//     16.9 k -> 17.4 k, FP32 34.0 k -> 35.3 k, FP16 61.0 k -> 69.3 k. Not
+//     faster: FP64 blocked (18.1 k -> 17.6-18.2 k), and SoA with 64-bit
+//     addresses except in FP32 (FP64 16.8 k -> 14.0 k, FP16 61.7 k -> 53.8 k,
+//     FP32 33.8 k -> 35.6 k).
 //   2Pop pull, D3Q27 RR 320^3: blocked FP32 23.5 k -> 25.0 k, FP16 46.7 k ->
 //     50.2 k. Slower in SoA (FP32 23.5 k -> 12.0 k, FP16 40.7 k -> 14.7 k).
-//   AA, D3Q19 256^3: SoA FP64 16.6 k -> 16.8 k, FP32 33.5 k -> 34.5 k, FP16
-//     55.8 k -> 66.3 k; blocked FP64 15.3 k -> 17.1 k, FP32 32.5 k -> 34.3 k,
+//   AA, D3Q19 256^3: SoA FP64 16.6 k -> 16.8 k, FP32 33.1 k -> 34.3 k, FP16
+//     55.8 k -> 67.0 k; blocked FP64 15.3 k -> 17.1 k, FP32 32.5 k -> 34.3 k,
 //     FP16 58.1 k -> 69.1 k.
 //   AA, D3Q27 RR 320^3: SoA FP32 20.8 k -> 23.4 k, FP16 32.0 k -> 42.3 k;
 //     blocked FP32 20.0 k -> 23.6 k, FP16 34.8 k -> 46.4 k.
@@ -645,7 +658,10 @@ static bool box_measured_faster(const lbm_handle* h, int kind)
     const size_t s = elem_bytes(h->d.storage_dtype);
     const bool soa = h->d.layout == LBM_SOA, blocked = h->d.layout == LBM_BLOCKED;
     if (kind == KIND_AA_ODD) return (soa || blocked) && (h->q == 19 || s < 8);
-    if (kind == KIND_PULL) return h->q == 19 ? ((blocked && s < 8) || (soa && s == 4)) : (blocked && s < 8);
+    if (kind == KIND_PULL) {
+        if (blocked) return s < 8;
+        return soa && h->q == 19 && (h->soa32() || s == 4);
+    }
     return false;
 }
 
