@@ -35,12 +35,12 @@ KERNEL_LABEL = {"2pop_pull": "2Pop pull", "aa": "AA even/odd"}
 
 def kernel_label(r) -> str:
     """The step kernel a headline run times (D3Q19, 256^3). On the built-in
-    cavity the library takes the position-driven pull kernel except for FP64
-    in the blocked layout, and the position-driven AA odd kernel in SoA and
-    the blocked layout (where they measured faster), the flag-driven ones
-    otherwise."""
+    cavity the library takes the position-driven pull kernel (FP64: blocks of
+    128 threads, three per CU) and the position-driven AA odd kernel in SoA
+    and the blocked layout, where they measured faster than the flag-driven
+    ones."""
     label = KERNEL_LABEL[r["scheme"]]
-    if r["scheme"] == "2pop_pull" and not (r["dtype"] == "f64" and r["layout"] == "blocked"):
+    if r["scheme"] == "2pop_pull" and r["layout"] in ("soa", "blocked"):
         label += ", position-driven"
     if r["scheme"] == "aa" and r["layout"] in ("soa", "blocked"):
         label += " (odd step position-driven)"
@@ -828,7 +828,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "D3Q19 lid-driven cavity 256^3 incl. walls, Re=1000, u_lid=0.05, "
                                "BGK, two-population scheme in pull form, blocked layout (the 19 streams of each "
-                               "run of 256 cells together), FP64 populations",
+                               "run of 256 cells together), position-driven kernel, FP64 populations",
                    "scheme": HEAD_SCHEME, "layout": HEAD_LAYOUT,
                    "cells": cav.cells, "fluid_cells": cav.fluid_cells, "omega": round(cav.omega, 6),
                    "parallelism": "single GPU"},

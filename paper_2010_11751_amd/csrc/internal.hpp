@@ -100,6 +100,7 @@ struct Field {
     uint64_t zrecip;       // ceil(2^64 / nz) (nz >= 2; else 0): floor(i / nz) = high word of i * zrecip
     uint64_t yrecip;       // ceil(2^64 / ny), the same for the row index (x ny + y) -> x
     int soa32;             // SoA whose streams and halo span under 4 GiB: 32-bit byte offsets suffice
+    int run_rows;          // blocked layout with nz equal to the run: each row is one run
 };
 
 // Largest block of the step kernels: the moment-space models (model >= 4)
@@ -155,13 +156,17 @@ inline int step_waves(int elem_bytes, int kind)
 // most 64 KiB per block, so at least two blocks). The size sits half a
 // block's share below the limit, so the count holds whatever the allocation
 // granularity. The kernels do not use it: it only caps residency.
+inline uint32_t residency_lds_blocks(int blocks_per_cu)
+{
+    const uint32_t blocks = (uint32_t)(blocks_per_cu < 2 ? 2 : blocks_per_cu);
+    const uint32_t v = (2u * 163840u / (2u * blocks + 1u)) / 1024u * 1024u;
+    return v < 65536u ? v : 65536u;
+}
+
 inline uint32_t residency_lds(int waves_per_simd, int block)
 {
     if (waves_per_simd <= 0) return 0;
-    const int b = (waves_per_simd * 256) / (block < 64 ? 64 : block);
-    const uint32_t blocks = (uint32_t)(b < 2 ? 2 : b);
-    const uint32_t v = (2u * 163840u / (2u * blocks + 1u)) / 1024u * 1024u;
-    return v < 65536u ? v : 65536u;
+    return residency_lds_blocks((waves_per_simd * 256) / (block < 64 ? 64 : block));
 }
 
 struct RelaxD {

@@ -752,38 +752,61 @@ __device__ __forceinline__ real_t<ST> box_wall_term(const Field& F, const BoxPos
 // cells next to a wall, and no edge-cell list (edges and corners take the
 // same path). The sums are those of the flag-driven kernels, operand for
 // operand.
-// SoA arrays under 4 GiB (F.soa32): the same kinds with every address an
-// unsigned 32-bit byte offset from one base, the start of the halo before
-// stream 0. A lane's choice between its own slot and the neighbour's is then
-// one 32-bit select, and each load or store takes the common base in scalar
-// registers, where two 64-bit pointers into two streams cost a select each.
-template <int Q, int MODEL, class ST, int KIND>
-__device__ __forceinline__ void box_step_soa32(const Field& F, const Relax<real_t<ST>>& rp, uint32_t i,
-                                               const BoxPos& p)
+// The same kinds with every address an unsigned 32-bit byte offset from one
+// base held in scalar registers. A lane's choice between its own slot and the
+// neighbour's is then one 32-bit select (written as arithmetic: the compiler
+// would otherwise branch per direction), where two 64-bit pointers into two
+// streams cost a select each and kept the loads from issuing together. Two
+// addressings qualify: SoA arrays under 4 GiB (F.soa32; the base is the start
+// of the halo before stream 0), and the blocked layout when every row of the
+// lattice is one run (F.run_rows: nz equal to the run length), where the
+// neighbour x - c_k of a fluid cell (1 <= z <= nz - 2) lies a constant number
+// of runs away and at most one lane over within its run, so its index is the
+// cell's own plus a constant.
+template <int Q>
+struct SoaOffsets {
+    uint32_t lane, ssz, sz;
+    __device__ __forceinline__ uint32_t own(int s) const { return lane + (uint32_t)s * ssz; }
+    template <int K, int SIGN>
+    __device__ __forceinline__ uint32_t nb(const Field& F, int s) const
+    {
+        return own(s) + (uint32_t)(offset<Q, K, SIGN>(F) * (int32_t)sz);
+    }
+};
+
+template <int Q>
+struct RunOffsets {
+    uint32_t lane, sz;  // lane: byte offset of (cell, slot 0)
+    __device__ __forceinline__ uint32_t own(int s) const { return lane + (uint32_t)s * kBlockCells * sz; }
+    template <int K, int SIGN>
+    __device__ __forceinline__ uint32_t nb(const Field& F, int s) const
+    {
+        constexpr int cx = SIGN * L<Q>::cx(K), cy = SIGN * L<Q>::cy(K), cz = SIGN * L<Q>::cz(K);
+        const int32_t runs = cx * F.ny + cy;  // one run per row
+        return own(s) + (uint32_t)((runs * Q * (int32_t)kBlockCells + cz) * (int32_t)sz);
+    }
+};
+
+template <int Q, int MODEL, class ST, int KIND, class A>
+__device__ __forceinline__ void box_step_off(const Field& F, const Relax<real_t<ST>>& rp, const BoxPos& p,
+                                             const A& ad, const char* src, char* dst)
 {
     using S = L<Q>;
     using R = real_t<ST>;
     using T = typename ST::T;
     constexpr bool pull = KIND == KIND_PULL_BOX;
-    constexpr uint32_t sz = sizeof(T);
-    const int64_t h = (int64_t)F.ny * F.nz + F.nz + 1;  // the largest neighbour offset
-    const char* const src = reinterpret_cast<const char*>(F.pop) - h * sz;
-    char* const dst = reinterpret_cast<char*>(pull ? F.out : F.pop) - h * sz;
-    const uint32_t lane = i * sz + (uint32_t)h * sz;
-    const uint32_t ssz = (uint32_t)F.stride * sz;  // bytes between streams (32-bit: the arrays fit)
-    auto off = [&](int k, int32_t d) -> uint32_t { return lane + (uint32_t)k * ssz + (uint32_t)(d * (int32_t)sz); };
-    // a if c else b, as arithmetic (a branch per direction otherwise)
-    auto pick = [](bool c, uint32_t a, uint32_t b) -> uint32_t { return b ^ ((a ^ b) & (0u - (uint32_t)c)); };
     auto ld = [&](uint32_t o) -> R { return R(*reinterpret_cast<const T*>(src + o)); };
     auto st = [&](uint32_t o, R v) { *reinterpret_cast<T*>(dst + o) = to_storage<ST>(v); };
+    // a if c else b, as arithmetic
+    auto pick = [](bool c, uint32_t a, uint32_t b) -> uint32_t { return b ^ ((a ^ b) & (0u - (uint32_t)c)); };
     if (!pull && !p.fluid) return;
     R g[Q];
     static_for<0, Q>([&](auto K) { g[K] = R(0); });
     if (p.fluid) {
         static_for<0, Q>([&](auto K) {
             constexpr int k = K;
-            if constexpr (k == S::rest) g[k] = ld(off(k, 0));
-            else g[k] = ld(pick(box_wall<Q, k, -1>(p), off(k, 0), off(S::opp(k), offset<Q, k, -1>(F))));
+            if constexpr (k == S::rest) g[k] = ld(ad.own(k));
+            else g[k] = ld(pick(box_wall<Q, k, -1>(p), ad.own(k), ad.template nb<k, -1>(F, S::opp(k))));
         });
         static_for<0, Q>([&](auto K) {
             constexpr int k = K;
@@ -796,12 +819,12 @@ __device__ __forceinline__ void box_step_soa32(const Field& F, const Relax<real_
         constexpr int k = K;
         if constexpr (pull) {
             const R wv = p.top ? lid_value<ST, S::opp(k)>(F) : R(0);
-            st(off(S::opp(k), 0), p.fluid ? g[k] : wv);
+            st(ad.own(S::opp(k)), p.fluid ? g[k] : wv);
         } else if constexpr (k == S::rest) {
-            st(off(k, 0), g[k]);
+            st(ad.own(k), g[k]);
         } else {
             const bool w = box_wall<Q, k, 1>(p);
-            st(pick(w, off(S::opp(k), 0), off(k, offset<Q, k, 1>(F))),
+            st(pick(w, ad.own(S::opp(k)), ad.template nb<k, 1>(F, k)),
                w ? g[k] + box_wall_term<Q, k, 1, ST, k>(F, p) : g[k]);
         }
     });
@@ -817,9 +840,22 @@ __device__ __forceinline__ void box_step_cell(const Field& F, const Relax<real_t
     const Acc<ST, LAYOUT, Q, true> a{(T*)F.pop, F.stride};
     const Acc<ST, LAYOUT, Q, true> o{(T*)(pull ? F.out : F.pop), F.stride};
     const BoxPos p = box_pos64(F, i);
+    constexpr uint32_t sz = sizeof(T);
     if constexpr (LAYOUT == LAYOUT_SOA) {
         if (F.soa32) {
-            box_step_soa32<Q, MODEL, ST, KIND>(F, rp, i, p);
+            const int64_t h = (int64_t)F.ny * F.nz + F.nz + 1;  // the largest neighbour offset
+            const SoaOffsets<Q> ad{(i + (uint32_t)h) * sz, (uint32_t)F.stride * sz, sz};
+            box_step_off<Q, MODEL, ST, KIND>(F, rp, p, ad, reinterpret_cast<const char*>(F.pop) - h * sz,
+                                             reinterpret_cast<char*>(pull ? F.out : F.pop) - h * sz);
+            return;
+        }
+    } else if constexpr (LAYOUT == LAYOUT_BLOCKED) {
+        if (F.run_rows) {
+            constexpr uint32_t B = kBlockCells;
+            const uint32_t j = i + (uint32_t)F.stride;  // past the halo runs
+            const RunOffsets<Q> ad{((j & ~(B - 1)) * (uint32_t)Q + (j & (B - 1))) * sz, sz};
+            box_step_off<Q, MODEL, ST, KIND>(F, rp, p, ad, reinterpret_cast<const char*>(F.pop),
+                                             reinterpret_cast<char*>(pull ? F.out : F.pop));
             return;
         }
     }

@@ -497,6 +497,7 @@ struct lbm_handle {
         F.zrecip = reciprocal64(d.nz);
         F.yrecip = reciprocal64(d.ny);
         F.soa32 = soa32() ? 1 : 0;
+        F.run_rows = d.layout == LBM_BLOCKED && d.nz == (int)kBlockCells ? 1 : 0;
         return F;
     }
     Launch base(int op) const
@@ -635,12 +636,12 @@ static bool zwrap_kind(int kind) { return kind == KIND_PULL || kind == KIND_AA_O
 // odd kinds have position-driven forms with no edge part. The library takes
 // them where they measured faster than the flag-driven ones (MLUPS,
 // flag-driven -> position-driven):
-//   2Pop pull, D3Q19 256^3: FP32 blocked 34.6 k -> 36.9 k; FP16 blocked
-//     67.2 k -> 76.4 k; SoA with 32-bit offsets (arrays under 4 GiB) FP64
-//     16.9 k -> 17.4 k, FP32 34.0 k -> 35.3 k, FP16 61.0 k -> 69.3 k. Not
-//     faster: FP64 blocked (18.1 k -> 17.6-18.2 k), and SoA with 64-bit
-//     addresses except in FP32 (FP64 16.8 k -> 14.0 k, FP16 61.7 k -> 53.8 k,
-//     FP32 33.8 k -> 35.6 k).
+//   2Pop pull, D3Q19 256^3: FP64 blocked 18.1 k -> 18.9 k (blocks of 128,
+//     three per CU, see run_kind); FP32 blocked 34.6 k -> 36.9 k; FP16
+//     blocked 67.2 k -> 76.4 k; SoA with 32-bit offsets (arrays under 4 GiB)
+//     FP64 16.9 k -> 17.7 k, FP32 34.0 k -> 35.3 k, FP16 61.0 k -> 69.3 k.
+//     Not faster: SoA with 64-bit addresses except in FP32 (FP64 16.8 k ->
+//     14.0 k, FP16 61.7 k -> 53.8 k, FP32 33.8 k -> 35.6 k).
 //   2Pop pull, D3Q27 RR 320^3: blocked FP32 23.5 k -> 25.0 k, FP16 46.7 k ->
 //     50.2 k. Slower in SoA (FP32 23.5 k -> 12.0 k, FP16 40.7 k -> 14.7 k).
 //   AA, D3Q19 256^3: SoA FP64 16.6 k -> 16.8 k, FP32 33.1 k -> 34.3 k, FP16
@@ -659,7 +660,7 @@ static bool box_measured_faster(const lbm_handle* h, int kind)
     const bool soa = h->d.layout == LBM_SOA, blocked = h->d.layout == LBM_BLOCKED;
     if (kind == KIND_AA_ODD) return (soa || blocked) && (h->q == 19 || s < 8);
     if (kind == KIND_PULL) {
-        if (blocked) return s < 8;
+        if (blocked) return s < 8 || h->q == 19;
         return soa && h->q == 19 && (h->soa32() || s == 4);
     }
     return false;
@@ -713,6 +714,17 @@ static int run_kind(lbm_handle* h, int kind)
     if (cpt == 1) {  // one launch, the edge part in the leading blocks
         L.kind = fast_kind(h, kind);
         L.lds = step_lds(h, L.kind);
+        if (L.kind == KIND_PULL_BOX && elem_bytes(h->d.storage_dtype) == 8 && h->d.block_size == 0 &&
+            !h->lds_override) {
+            // FP64 position-driven pull: blocks of 128 threads, three per CU
+            // (six waves). Measured on the 256^3 cavity, blocked layout:
+            // 18.9 k MLUPS, against 18.2 k for blocks of 256 at two waves per
+            // SIMD, 18.6 k / 18.4 k for four / five blocks of 128, 17.7 k
+            // for six blocks of 64; SoA 17.7 k against 17.4 k.
+            L.block = 128;
+            L.grid = grid_for((uint64_t)h->ntot, 128);
+            L.lds = residency_lds_blocks(3);
+        }
         if (neighbours && n_slow > 0 && L.kind != KIND_PULL_BOX && L.kind != KIND_AA_ODD_BOX &&
             L.kind != KIND_PULL_WRAP && L.kind != KIND_AA_ODD_WRAP) {
             L.slow_list = zwrap_kind(kind) ? h->slow_list_z : h->slow_list;

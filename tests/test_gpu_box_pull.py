@@ -180,3 +180,28 @@ def test_wrap_kernels_equal_flag_kernels(lbm, monkeypatch, layout, scheme, dtype
         sim.step(41)
         got[kernel] = sim.populations().cpu()
     assert torch.equal(got["box"], got["flag"])
+
+
+@pytest.mark.parametrize("scheme", ("2pop_pull", "aa"))
+@pytest.mark.parametrize("q,coll", [(19, "trt"), (27, "rr")])
+def test_box_kernels_rows_of_one_run(lbm, monkeypatch, q, coll, scheme):
+    """Blocked layout with rows of exactly one run (nz = 256): the
+    position-driven kernels address neighbours as the cell's own index plus a
+    constant; FP64 against the oracle, FP16 bit for bit against the
+    flag-driven kernels."""
+    nx, ny, nz, omega, lid = 6, 5, 256, 1.8, (0.04, 0.01, 0.0)
+    print(f"case: rows of one run, {scheme} q={q} {coll}", flush=True)
+    sim = lattice(lbm, monkeypatch, "box", q, nx, ny, nz, scheme=scheme, collision=coll, omega=omega,
+                  layout="blocked", lid_velocity=lid)
+    ref = O.Simulation(O.Config(q=q, nx=nx, ny=ny, nz=nz, model=O.MODELS[coll], omega=omega, u_lid=lid), "ref")
+    for n in (1, 4, 3):
+        sim.step(n)
+        ref.step(n)
+        assert np.abs(sim.populations().cpu().numpy() - ref.populations()).max() <= TOL, n
+    got = {}
+    for kernel in ("box", "flag"):
+        s16 = lattice(lbm, monkeypatch, kernel, q, nx, ny, nz, scheme=scheme, collision=coll, omega=omega,
+                      layout="blocked", lid_velocity=lid, dtype="f16")
+        s16.step(23)
+        got[kernel] = s16.populations().cpu()
+    assert torch.equal(got["box"], got["flag"])
