@@ -714,13 +714,15 @@ static int run_kind(lbm_handle* h, int kind)
     if (cpt == 1) {  // one launch, the edge part in the leading blocks
         L.kind = fast_kind(h, kind);
         L.lds = step_lds(h, L.kind);
-        if (L.kind == KIND_PULL_BOX && elem_bytes(h->d.storage_dtype) == 8 && h->d.block_size == 0 &&
-            !h->lds_override) {
+        if ((L.kind == KIND_PULL_BOX || L.kind == KIND_PULL_WRAP) && elem_bytes(h->d.storage_dtype) == 8 &&
+            h->d.block_size == 0 && !h->lds_override) {
             // FP64 position-driven pull: blocks of 128 threads, three per CU
             // (six waves). Measured on the 256^3 cavity, blocked layout:
             // 18.9 k MLUPS, against 18.2 k for blocks of 256 at two waves per
             // SIMD, 18.6 k / 18.4 k for four / five blocks of 128, 17.7 k
-            // for six blocks of 64; SoA 17.7 k against 17.4 k.
+            // for six blocks of 64; SoA 17.7 k against 17.4 k; the periodic
+            // 256^3 box, blocked: 18.5 k against 17.4 k. (The AA odd kinds
+            // measured slower this way.)
             L.block = 128;
             L.grid = grid_for((uint64_t)h->ntot, 128);
             L.lds = residency_lds_blocks(3);
