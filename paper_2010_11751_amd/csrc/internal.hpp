@@ -141,11 +141,15 @@ constexpr int min_step_waves(int q, int elem_bytes, int kind)
 // uncapped; FP32: 32.3 k uncapped, 31.4 k at four), 6 and 7 the z-wrap
 // variants of 5 and 4, 8 the position-driven 2Pop pull of the built-in cavity
 // (blocked layout, FP64: 18.2 k at two waves, 17.6 k at three, 17.5 k
-// uncapped; FP32 and FP16 within 1 % of their best uncapped).
+// uncapped; FP32 and FP16 within 1 % of their best uncapped; the default FP64
+// launch is blocks of 128, three per CU, set in run_kind), 9 its AA odd
+// kind, 10 and 11 the position-driven pull and AA odd kinds of the periodic
+// box.
 inline int step_waves(int elem_bytes, int kind)
 {
     if (kind == 8) return elem_bytes == 8 ? 2 : 0;
-    if (kind == 9 || kind == 10 || kind == 11) return elem_bytes == 8 ? 3 : 0;
+    if (kind == 9) return elem_bytes == 8 ? 2 : 0;  // FP64 SoA 16.8 k -> 17.0 k, blocked 17.1 k -> 17.3 k at 2
+    if (kind == 10 || kind == 11) return elem_bytes == 8 ? 3 : 0;
     if (elem_bytes == 8) return (kind == 4 || kind >= 5) ? 3 : 2;
     if (elem_bytes == 4) return (kind == 4 || kind == 2 || kind >= 5) ? 0 : 4;
     return 0;
