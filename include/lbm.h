@@ -51,7 +51,18 @@
  *                           residency cap chosen by storage type
  *   LBM_NO_RESIDENCY_CAP    no residency cap
  *   LBM_NO_GRAPH            no captured step graphs for small lattices
- *   LBM_NO_OVERLAP          edge-cell kernel on the handle's stream
+ *   LBM_PULL_KERNEL=box|flag  the 2Pop pull step on the built-in cavity or
+ *                           periodic box: "box" the kernel that takes its
+ *                           wall and wrap decisions from the cell's position,
+ *                           "flag" the one driven by the flag byte and the
+ *                           edge-cell list; unset, the one measured faster for
+ *                           the lattice, storage type and layout
+ *   LBM_AA_KERNEL=box|flag  the same for the AA odd step
+ *   LBM_SPLIT_STEP          the edge-cell part as a second kernel on a second
+ *                           stream instead of the leading blocks of the step
+ *                           kernel
+ *   LBM_NO_OVERLAP          with LBM_SPLIT_STEP: the edge-cell kernel on the
+ *                           handle's stream
  *   LBM_VERBOSE             print the stride trials to stderr
  *   LBM_REVERSE_BLOCKS      step kernels visit the cells in reverse block and
  *                           list order (a traversal-order check: every
