@@ -618,7 +618,7 @@ static int init_state(lbm_handle* h, const double* rho, const double* u)
 
 // One kernel kind over the lattice: the fast part over all cells, then, for
 // the kinds that reach neighbours, the slow part over the listed cells.
-static uint32_t step_lds(const lbm_handle* h, int kind)
+static uint32_t step_lds(const lbm_handle* h, int kind, int block)
 {
     if (h->lds_override)
         return kind == KIND_AA_ODD || kind == KIND_2POP || kind == KIND_SWAP_STREAM || kind == KIND_PULL ||
@@ -630,7 +630,7 @@ static uint32_t step_lds(const lbm_handle* h, int kind)
     // and needs the third wave to hide it (15.8 k MLUPS at three, 15.0 k at
     // two, where the other nine models gain 1 % at two).
     if (kind == KIND_AA_ODD_BOX && elem_bytes(h->d.storage_dtype) == 8 && h->d.collision == LBM_K) waves = 3;
-    return residency_lds(waves, h->block);
+    return residency_lds(waves, block);
 }
 
 // Kind of the fast launch: the pull and AA odd kinds have variants for
@@ -708,7 +708,7 @@ static int run_kind(lbm_handle* h, int kind)
 {
     Launch L = h->base(OP_STEP);
     L.kind = kind;
-    L.lds = step_lds(h, kind);
+    L.lds = step_lds(h, kind, L.block);
     if (h->fused && kind != KIND_SWAP_COLLIDE && kind != KIND_SWAP_STREAM) {
         L.op = OP_STEP_ALL;
         return run(h, L);
@@ -718,9 +718,20 @@ static int run_kind(lbm_handle* h, int kind)
     const uint32_t n_slow = zwrap_kind(kind) ? h->n_slow_z : h->n_slow;
     if (cpt == 1) {  // one launch, the edge part in the leading blocks
         L.kind = fast_kind(h, kind);
-        L.lds = step_lds(h, L.kind);
-        if ((L.kind == KIND_PULL_BOX || L.kind == KIND_PULL_WRAP) && elem_bytes(h->d.storage_dtype) == 8 &&
-            h->d.block_size == 0 && !h->lds_override) {
+        const size_t s = elem_bytes(h->d.storage_dtype);
+        const bool auto_shape = h->d.block_size == 0 && !h->lds_override;
+        if (auto_shape && s < 8 && h->q == 19 &&
+            ((L.kind == KIND_PULL_BOX && s == 2 && h->d.layout == LBM_BLOCKED) ||
+             ((kind == KIND_AA_EVEN || kind == KIND_AA_ODD) && h->d.layout == LBM_SOA && box_kind(h, KIND_AA_ODD)))) {
+            // Blocks of 512 at the same resident waves per SIMD, where they
+            // measured faster on the 256^3 cavity: FP16 blocked pull 75.3 k ->
+            // 77.1 k MLUPS; AA in SoA (both steps) FP32 34.6 k -> 35.2 k, FP16
+            // 67.9 k -> 68.6 k. (FP32 pull: 36.8 k -> 36.5 k.)
+            L.block = std::min(512, max_step_block(h->q, h->d.collision, (int)s));
+            L.grid = grid_for((uint64_t)h->ntot, L.block);
+        }
+        L.lds = step_lds(h, L.kind, L.block);
+        if ((L.kind == KIND_PULL_BOX || L.kind == KIND_PULL_WRAP) && s == 8 && auto_shape) {
             // FP64 position-driven pull: blocks of 128 threads, three per CU
             // (six waves). Measured on the 256^3 cavity, blocked layout:
             // 18.9 k MLUPS, against 18.2 k for blocks of 256 at two waves per
@@ -786,11 +797,11 @@ static int run_kind_overlapped(lbm_handle* h, int kind)
     HIP_TRY(hipEventRecord(h->join, h->aux), "hipEventRecord");
     Launch L = h->base(OP_STEP);
     L.kind = fast_kind(h, kind);
-    L.lds = step_lds(h, kind);
     if (h->cpt > 1) {
         L.block = std::min(h->block, 256);
         L.grid = grid_for(((uint64_t)h->ntot + h->cpt - 1) / h->cpt, L.block);
     }
+    L.lds = step_lds(h, kind, L.block);
     int rc = run(h, L);
     if (rc) return rc;
     HIP_TRY(hipStreamWaitEvent(h->stream, h->join, 0), "hipStreamWaitEvent");
