@@ -205,3 +205,20 @@ def test_box_kernels_rows_of_one_run(lbm, monkeypatch, q, coll, scheme):
         s16.step(23)
         got[kernel] = s16.populations().cpu()
     assert torch.equal(got["box"], got["flag"])
+
+
+@pytest.mark.parametrize("dtype", ("f64", "f32", "f16"))
+@pytest.mark.parametrize("scheme,layout", [("2pop_pull", "blocked"), ("2pop_pull", "soa"), ("aa", "soa")])
+def test_launch_shapes_change_no_result(lbm, scheme, layout, dtype):
+    """The library's own launch shapes (FP64 pull: blocks of 128, three per
+    CU; FP16 pull and FP32 / FP16 AA: blocks of 512) against fixed blocks of
+    256 and 64: the same bits."""
+    dims = (9, 7, 256) if layout == "blocked" else (13, 11, 70)
+    got = []
+    for block in (0, 256, 64):
+        sim = lbm.Lattice(19, *dims, scheme=scheme, collision="trt", omega=1.85, lid_velocity=(0.05, 0.01, 0.0),
+                          layout=layout, dtype=dtype, block_size=block)
+        sim.step(21)
+        got.append(sim.populations().cpu())
+    assert torch.equal(got[0], got[1])
+    assert torch.equal(got[0], got[2])
